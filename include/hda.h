@@ -1,0 +1,175 @@
+/* hda.h -- out-of-band-metadata allocators for memory the allocator never
+ * reads, replayed on an AMD Instinct MI355X (gfx950).
+ *
+ * The allocators are those of "Host-Based Allocators for Device Memory"
+ * (Bell, Kumar, Gill): first fit, next fit, best fit (Sec. II-A, Sec. IV,
+ * Alg. 1-3) and segregated fit (Sec. II-B, Sec. V-A, Alg. 4-5).  The managed
+ * arena is virtual: the library hands out byte offsets into [0, arena_bytes)
+ * and never reads, writes or backs that range (Sec. I: large arenas come from
+ * the driver, fine-grained allocation happens elsewhere, and the allocator
+ * cannot read the memory it manages).  A caller that owns real memory adds its
+ * base pointer to the offsets.
+ *
+ * Conventions shared by every entry point
+ *  - Sizes and offsets are bytes (int64).  A request of `size` bytes is
+ *    normalised to s = max(align, roundup(size, align)); a block is always
+ *    taken from the low end of the chosen free block (Alg. 1, Alg. 4).
+ *  - Allocation failure is the value -1 (HDA_FAIL), never an error.
+ *  - Every error leaves the heap's state unchanged.
+ *  - Pointers documented as "device" must be device-accessible memory
+ *    (hipMalloc / torch CUDA tensors) that stays alive until the stream
+ *    work that uses them has completed; the library never frees them.
+ *  - Functions taking a `stream` enqueue work on that hipStream_t (NULL = the
+ *    null stream) and return without waiting, unless stated otherwise.
+ */
+#ifndef HDA_H
+#define HDA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Algorithms (per heap). */
+enum {
+  HDA_FIRST_FIT = 0, /* lowest-address free block with size >= s (Sec. II-A) */
+  HDA_NEXT_FIT = 1,  /* first fit resumed at a rover (Sec. II-A, Sec. IV)    */
+  HDA_BEST_FIT = 2,  /* smallest block >= s, lowest address on ties (Alg. 3) */
+  HDA_SEG_FIT = 3    /* power-of-two classes + bitmap, LIFO lists (Alg. 4-5) */
+};
+
+/* Status codes. */
+enum {
+  HDA_OK = 0,
+  HDA_FAIL = -1,      /* allocation: nothing fits (a result, not an error)   */
+  HDA_E_INVAL = -2,   /* bad argument (see each function)                    */
+  HDA_E_BADFREE = -3, /* free of an offset that is not a live block's start  */
+  HDA_E_NOMETA = -4,  /* per-heap metadata capacity exhausted                */
+  HDA_E_DEVICE = -5,  /* a HIP runtime call failed                           */
+  HDA_E_BUSY = -6,    /* resource in use (service running, budget held)      */
+  HDA_E_RANGE = -7    /* an output buffer is too small                       */
+};
+
+/* ------------------------------------------------------------------------ */
+/* Batched replay (many independent heaps, one persistent launch).          */
+/* ------------------------------------------------------------------------ */
+
+/* Request encoding, one int64 per request, heap h owning
+ * req[req_off[h] .. req_off[h+1]):
+ *   req >= 0 : allocate req bytes;           result = byte offset, or -1.
+ *   req <  0 : free one live block: r = (uint32_t)~req is a uniform 32-bit
+ *              draw and the freed block is live[(r * L) >> 32], where live[]
+ *              lists the heap's live blocks (a successful allocation appends
+ *              its block; a free moves the last entry into the freed slot)
+ *              and L is their number.  result = the freed offset, or -1 when
+ *              no block is live (the request then does nothing).
+ * A request that would exceed the heap's metadata capacity yields
+ * HDA_E_NOMETA as its result and changes nothing.
+ *
+ * Canonical state of a heap, int64 words (all addresses/sizes in bytes):
+ *   n_free, (addr, size) x n_free in address order,
+ *   n_live, (addr, size) x n_live in live[] order,
+ *   rover (next fit: the byte address the next search resumes at) or -1,
+ *   class bitmap (segregated fit; bit k <=> class k list non-empty) or 0,
+ *   segregated fit only: for each class k = 0..63 (sizes in [2^k, 2^(k+1))):
+ *     len_k, then the block addresses from list head to tail.
+ */
+typedef struct hda_tuning {
+  int32_t heaps_per_group; /* waves (= heaps in flight) per workgroup; 0 = auto */
+  int32_t lds_free;        /* free-table entries kept in LDS per heap (mult. of 64); 0 = auto */
+  int32_t lds_live;        /* live-table entries kept in LDS per heap (mult. of 64); 0 = auto */
+  int32_t groups;          /* persistent workgroups; 0 = fill the device       */
+} hda_tuning;
+
+typedef struct hda_batch_desc {
+  int64_t n_heaps;          /* H >= 0                                          */
+  const int64_t *arena;     /* device [H]: arena bytes (> 0, multiple of align) */
+  const int64_t *align;     /* device [H]: alignment bytes (power of two)       */
+  const int32_t *algo;      /* device [H]: HDA_FIRST_FIT .. HDA_SEG_FIT         */
+  const int64_t *req_off;   /* device [H+1]: CSR offsets into req/res           */
+  const int64_t *req;       /* device [req_off[H]]: encoded requests            */
+  int64_t *res;             /* device [req_off[H]]: results (written)           */
+  const int32_t *order;     /* device [H] or NULL: heap processing order
+                               (a permutation; NULL = 0..H-1)                   */
+  int64_t *state;           /* device or NULL: canonical states (written)       */
+  const int64_t *state_off; /* device [H+1]: heap h's state slot is
+                               state[state_off[h] .. state_off[h+1])            */
+  int64_t *state_len;       /* device [H]: words of heap h's state (written;
+                               set even when the slot is too small)             */
+  int32_t *status;          /* device [H]: HDA_OK or the heap's first error
+                               (E_INVAL bad heap params, E_NOMETA capacity,
+                               E_RANGE state slot too small)                    */
+  int64_t meta_free;        /* free-table capacity per heap (entries)           */
+  int64_t meta_live;        /* live-table capacity per heap (entries)           */
+  void *workspace;          /* device scratch of hda_replay_workspace() bytes   */
+  size_t workspace_bytes;
+  hda_tuning tuning;
+} hda_batch_desc;
+
+/* Bytes of device scratch hda_replay needs for `d` (reads only n_heaps,
+ * meta_free, meta_live and tuning).  Returns 0 on invalid arguments. */
+size_t hda_replay_workspace(const hda_batch_desc *d);
+
+/* Resolve the tuning actually used for `d` (autotuned defaults filled in). */
+int hda_replay_resolve(const hda_batch_desc *d, hda_tuning *out);
+
+/* Enqueue the replay of every heap of `d` on `stream` as one persistent
+ * kernel launch.  Heaps are pulled from a device queue in `order`; each heap
+ * is replayed in request order by one wavefront, so results are identical to
+ * sequential in-order replay of each heap whatever the tuning.
+ * Returns HDA_E_INVAL for null or inconsistent descriptor fields,
+ * HDA_E_RANGE if workspace_bytes is too small, HDA_E_DEVICE on launch
+ * failure; per-heap problems are reported through `status`. */
+int hda_replay(const hda_batch_desc *d, void *stream);
+
+/* The per-heap-launch baseline: the same kernel body launched once per heap
+ * (H launches of one wavefront each, in `order`, on `stream`). */
+int hda_replay_per_heap(const hda_batch_desc *d, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Single heaps driven call by call (Alg. 6 init; Alg. 1-5 per call).       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct hda_heap hda_heap; /* opaque, library-owned */
+
+/* Create a heap over a virtual arena of arena_bytes (Alg. 6: one free block
+ * [0, arena_bytes)).  Metadata lives in device memory owned by the library:
+ * meta_cap bounds both the free-table and the live-table entries (0 = 4096).
+ * HDA_E_INVAL: align not a power of two, arena_bytes == 0 or not a multiple
+ * of align, arena_bytes / align >= 2^32, unknown algo, out == NULL.
+ * HDA_E_NOMETA: the metadata budget (hda_set_meta_budget) is exhausted.
+ * Synchronous. */
+int hda_heap_create(uint64_t arena_bytes, uint64_t align, int algo,
+                    uint32_t meta_cap, hda_heap **out);
+
+/* Release a heap and return its metadata to the budget.  Synchronous. */
+int hda_heap_destroy(hda_heap *h);
+
+/* Allocate `size` bytes: returns the byte offset, -1 when nothing fits, or
+ * HDA_E_NOMETA / HDA_E_DEVICE / HDA_E_INVAL (h == NULL).  Synchronous: one
+ * kernel launch on the library's stream. */
+int64_t hda_alloc(hda_heap *h, uint64_t size);
+
+/* Free the block starting at `offset`; neighbours that are free are merged
+ * (Alg. 2, Alg. 5).  HDA_E_BADFREE if `offset` is not the start of a live
+ * block.  Synchronous. */
+int hda_free(hda_heap *h, int64_t offset);
+
+/* Copy the heap's canonical state (format above) into host buffer `buf` of
+ * `cap` words; *len receives the words needed.  HDA_E_RANGE if cap < *len.
+ * Synchronous. */
+int hda_heap_state(const hda_heap *h, int64_t *buf, size_t cap, size_t *len);
+
+/* Metadata budget (bytes of device memory all live heaps may hold);
+ * 0 = unlimited (the default).  Returns the bytes currently held. */
+int64_t hda_set_meta_budget(int64_t bytes);
+
+/* Static description of an error code. */
+const char *hda_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HDA_H */

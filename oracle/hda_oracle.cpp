@@ -1,0 +1,385 @@
+// Allocator replay oracle -- TEST INFRASTRUCTURE ONLY.
+//
+// A plain, slow, sequential CPU model of the allocators in "Host-Based
+// Allocators for Device Memory" (Bell, Kumar, Gill): first fit, next fit and
+// best fit over an address-ordered free list (Sec. II-A, Sec. IV, Alg. 1-3),
+// and segregated fit over address-keyed block records threaded into per-class
+// free lists with a class-availability bitmap (Sec. III-C, Sec. V-A,
+// Alg. 4-5).  No metadata lives in the managed memory: the arena is never
+// touched, only described.
+//
+// Only the test-suite, the smoke check and the CPU-baseline leg of the
+// benchmark may load this library.  The GPU path shares no code with it.
+//
+// Plain library containers are used on purpose (std::map keyed by address
+// plays the role of the paper's sorted lists and of its address-keyed hash
+// table); nothing is blocked, fused or reordered.
+//
+// Readings where the paper is silent or inconsistent (each applied here):
+//  * Sizes are normalised to s = max(g, roundup(req, g)); a request larger
+//    than the arena fails (the paper passes sizes through unchanged).
+//  * The block handed out is the low end of the chosen free block (Alg. 1,
+//    Alg. 4: the free entry's address advances by the size).
+//  * Best fit picks the smallest block with size >= s, lowest address among
+//    equals; an exact size match is taken (Sec. II-A prose; Alg. 3's loop
+//    exits on an exact match and starts from a sentinel).
+//  * Next fit keeps a rover byte address, set to a+s after every successful
+//    allocation and left alone otherwise; a search starts at the first free
+//    block whose end lies above the rover and wraps around once.
+//  * Deallocation merges with the free predecessor when it ends exactly at
+//    the freed address and with the free successor when it starts exactly at
+//    the freed end; in the three-way case the successor entry is removed
+//    (Alg. 2 with equality tests).
+//  * Segregated fit: class k holds sizes in [2^k, 2^(k+1)) bytes; a request
+//    of s bytes is served from the lowest non-empty class >= ceil(log2 s)
+//    found with find-first-set on the bitmap, never from class
+//    ceil(log2 s)-1 (Sec. II-B; the "nearly 4x larger" remark of Sec. V-A
+//    fixes this 0-based class index).  Lists are LIFO: pop and push at the
+//    head (Alg. 4, Alg. 5).  A class bit is cleared exactly when its list
+//    becomes empty.  On free, free neighbours are unlinked from their lists
+//    first and the merged block is always pushed at the head of the list of
+//    floor(log2 size).  The null link is -1 (offset 0 is a valid address).
+//  * No allocation ever fails with an error: a request nothing can satisfy
+//    returns -1 and leaves the state (and the rover) unchanged.
+//  * Replay driver (not part of the paper): a free request carries a uniform
+//    32-bit draw r; the freed block is live[(r * L) >> 32] where live[] lists
+//    the live blocks (append on success, swap-with-last removal on free) and
+//    L = |live|.  With no live block the request does nothing and yields -1.
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <thread>
+#include <vector>
+
+namespace {
+
+constexpr int FF = 0, NF = 1, BF = 2, SF = 3;
+constexpr int64_t NIL = -1;
+constexpr int E_INVAL = -2, E_BADFREE = -3;
+
+int floor_log2(uint64_t x) {  // x >= 1
+    int k = -1;
+    while (x) { x >>= 1; ++k; }
+    return k;
+}
+int ceil_log2(uint64_t x) {   // x >= 1: smallest k with 2^k >= x
+    int k = 0;
+    while ((uint64_t(1) << k) < x) ++k;
+    return k;
+}
+
+struct SfRecord {             // Sec. III-C: what a block header would hold
+    int64_t size;
+    bool free;
+    int64_t prev_adj;         // address of the block ending at this one's start
+    int64_t next_free;        // free-list links (addresses)
+    int64_t prev_free;
+};
+
+struct Heap {
+    int algo;
+    int64_t A, g;
+    // in-use blocks, address -> size (the "used list")
+    std::map<int64_t, int64_t> used;
+    // replay-driver order of the live blocks
+    std::vector<int64_t> live;
+    // sequential fits: address-ordered free list, address -> size
+    std::map<int64_t, int64_t> fl;
+    int64_t rover = 0;
+    // segregated fit: address-keyed records, list heads, availability bitmap
+    std::map<int64_t, SfRecord> ht;
+    int64_t head[64];
+    uint64_t bitmap = 0;
+    // instrumentation
+    uint64_t examined = 0;    // free entries inspected by a fit search
+    uint64_t touched = 0;     // segregated-fit records read or written
+
+    Heap(int a, int64_t arena, int64_t align) : algo(a), A(arena), g(align) {
+        // Alg. 6: the free list starts as the single block [0, A).
+        for (auto& h : head) h = NIL;
+        if (algo == SF) {
+            ht[0] = SfRecord{A, true, NIL, NIL, NIL};
+            push(0);
+        } else {
+            fl[0] = A;
+        }
+    }
+
+    // ---- segregated-fit list primitives (Alg. 4, Alg. 5) ----
+    void push(int64_t a) {
+        SfRecord& r = ht.at(a);
+        int c = floor_log2(uint64_t(r.size));
+        r.prev_free = NIL;
+        r.next_free = head[c];
+        if (head[c] != NIL) { ht.at(head[c]).prev_free = a; ++touched; }
+        head[c] = a;
+        bitmap |= uint64_t(1) << c;
+        ++touched;
+    }
+    void unlink(int64_t a) {
+        SfRecord& r = ht.at(a);
+        int c = floor_log2(uint64_t(r.size));
+        if (r.prev_free != NIL) { ht.at(r.prev_free).next_free = r.next_free; ++touched; }
+        else head[c] = r.next_free;
+        if (r.next_free != NIL) { ht.at(r.next_free).prev_free = r.prev_free; ++touched; }
+        if (head[c] == NIL) bitmap &= ~(uint64_t(1) << c);
+        r.next_free = r.prev_free = NIL;
+        ++touched;
+    }
+
+    // ---- allocation ----
+    int64_t alloc(int64_t req) {
+        if (req < 0 || req > A) return -1;
+        int64_t s = (req + g - 1) / g * g;
+        if (s == 0) s = g;
+        if (s > A) return -1;
+        int64_t a = (algo == SF) ? alloc_sf(s) : alloc_seq(s);
+        if (a >= 0) { used[a] = s; live.push_back(a); }
+        return a;
+    }
+
+    int64_t alloc_seq(int64_t s) {
+        auto pick = fl.end();
+        if (algo == FF) {            // lowest address with size >= s
+            for (auto it = fl.begin(); it != fl.end(); ++it) {
+                ++examined;
+                if (it->second >= s) { pick = it; break; }
+            }
+        } else if (algo == BF) {     // min (size, address) with size >= s
+            for (auto it = fl.begin(); it != fl.end(); ++it) {
+                ++examined;
+                if (it->second >= s &&
+                    (pick == fl.end() || it->second < pick->second)) pick = it;
+                if (it->second == s) break;
+            }
+        } else {                     // NF: resume at the block holding the rover
+            auto start = fl.begin();
+            while (start != fl.end() && start->first + start->second <= rover) ++start;
+            if (start == fl.end()) start = fl.begin();
+            auto it = start;
+            for (size_t n = 0; n < fl.size(); ++n) {
+                ++examined;
+                if (it->second >= s) { pick = it; break; }
+                if (++it == fl.end()) it = fl.begin();
+            }
+        }
+        if (pick == fl.end()) return -1;
+        // Alg. 1: take the low end; shrink the free entry or remove it.
+        int64_t a = pick->first, bsize = pick->second;
+        fl.erase(pick);
+        if (bsize > s) fl[a + s] = bsize - s;
+        if (algo == NF) rover = a + s;
+        return a;
+    }
+
+    int64_t alloc_sf(int64_t s) {
+        int k = ceil_log2(uint64_t(s));
+        uint64_t m = (k >= 64) ? 0 : (bitmap & (~uint64_t(0) << k));
+        if (m == 0) return -1;
+        int c = __builtin_ctzll(m);
+        int64_t a = head[c];
+        unlink(a);
+        SfRecord& it = ht.at(a);
+        it.free = false;
+        ++touched;
+        if (it.size > s) {           // split off the surplus, push it
+            int64_t b = a + s, r = it.size - s, old_end = a + it.size;
+            it.size = s;
+            ht[b] = SfRecord{r, true, a, NIL, NIL};
+            push(b);
+            if (old_end < A) { ht.at(old_end).prev_adj = b; ++touched; }
+        }
+        return a;
+    }
+
+    // ---- deallocation ----
+    int dealloc(int64_t x) {
+        auto u = used.find(x);
+        if (u == used.end()) return E_BADFREE;
+        int64_t s = u->second;
+        used.erase(u);
+        auto lv = std::find(live.begin(), live.end(), x);
+        *lv = live.back();
+        live.pop_back();
+        if (algo == SF) dealloc_sf(x); else dealloc_seq(x, s);
+        return 0;
+    }
+
+    void dealloc_seq(int64_t x, int64_t s) {
+        // Alg. 2: predecessor = last free block below x, successor = next.
+        auto succ = fl.upper_bound(x);
+        auto pred = (succ == fl.begin()) ? fl.end() : std::prev(succ);
+        bool left = pred != fl.end() && pred->first + pred->second == x;
+        bool right = succ != fl.end() && succ->first == x + s;
+        if (left && right) {
+            pred->second += s + succ->second;
+            fl.erase(succ);
+        } else if (left) {
+            pred->second += s;
+        } else if (right) {
+            int64_t sz = succ->second;
+            fl.erase(succ);
+            fl[x] = s + sz;
+        } else {
+            fl[x] = s;
+        }
+    }
+
+    void dealloc_sf(int64_t x) {
+        SfRecord it = ht.at(x);
+        ++touched;
+        int64_t start = x, end = x + it.size, prev_adj = it.prev_adj;
+        bool left = it.prev_adj != NIL && ht.at(it.prev_adj).free;
+        bool right = end < A && ht.at(end).free;
+        touched += (it.prev_adj != NIL) + (end < A);
+        if (left) {
+            int64_t l = it.prev_adj;
+            unlink(l);
+            start = l;
+            prev_adj = ht.at(l).prev_adj;
+            ht.erase(x);
+        }
+        if (right) {
+            int64_t r = end;
+            end = r + ht.at(r).size;
+            unlink(r);
+            ht.erase(r);
+        }
+        SfRecord& m = ht[start];
+        m.size = end - start;
+        m.free = true;
+        m.prev_adj = prev_adj;
+        if (end < A) { ht.at(end).prev_adj = start; ++touched; }
+        push(start);
+    }
+
+    // ---- canonical state ----
+    // [n_free, (addr,size)*n_free by address, n_live, (addr,size)*n_live in
+    //  live order, rover (next fit) or -1, bitmap (segregated fit) or 0,
+    //  segregated fit only: for each class 0..63: len, addresses head->tail]
+    std::vector<int64_t> dump() const {
+        std::vector<int64_t> o;
+        std::vector<std::pair<int64_t, int64_t>> fb;
+        if (algo == SF) {
+            for (auto& kv : ht) if (kv.second.free) fb.push_back({kv.first, kv.second.size});
+        } else {
+            for (auto& kv : fl) fb.push_back(kv);
+        }
+        o.push_back(int64_t(fb.size()));
+        for (auto& p : fb) { o.push_back(p.first); o.push_back(p.second); }
+        o.push_back(int64_t(live.size()));
+        for (int64_t a : live) { o.push_back(a); o.push_back(used.at(a)); }
+        o.push_back(algo == NF ? rover : -1);
+        o.push_back(algo == SF ? int64_t(bitmap) : 0);
+        if (algo == SF) {
+            for (int c = 0; c < 64; ++c) {
+                std::vector<int64_t> lst;
+                for (int64_t a = head[c]; a != NIL; a = ht.at(a).next_free) lst.push_back(a);
+                o.push_back(int64_t(lst.size()));
+                o.insert(o.end(), lst.begin(), lst.end());
+            }
+        }
+        return o;
+    }
+};
+
+bool valid_params(int algo, int64_t arena, int64_t align) {
+    if (algo < 0 || algo > 3) return false;
+    if (align <= 0 || (align & (align - 1))) return false;
+    if (arena <= 0 || arena % align) return false;
+    if (arena / align >= (int64_t(1) << 32)) return false;
+    return true;
+}
+
+// Replay one heap's requests in order (see the replay-driver reading above).
+void replay_one(Heap& h, int64_t n, const int64_t* req, int64_t* res) {
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t q = req[i];
+        if (q >= 0) {
+            res[i] = h.alloc(q);
+        } else if (h.live.empty()) {
+            res[i] = -1;
+        } else {
+            uint64_t r = uint32_t(~uint64_t(q));
+            uint64_t idx = (r * uint64_t(h.live.size())) >> 32;
+            int64_t x = h.live[idx];
+            h.dealloc(x);
+            res[i] = x;
+        }
+    }
+}
+
+int64_t copy_state(const Heap& h, int64_t* buf, int64_t cap) {
+    std::vector<int64_t> st = h.dump();
+    if (buf && int64_t(st.size()) <= cap) std::memcpy(buf, st.data(), st.size() * 8);
+    return int64_t(st.size());
+}
+
+}  // namespace
+
+extern "C" {
+
+void* orc_heap_new(int algo, int64_t arena, int64_t align) {
+    if (!valid_params(algo, arena, align)) return nullptr;
+    return new Heap(algo, arena, align);
+}
+void orc_heap_delete(void* h) { delete static_cast<Heap*>(h); }
+int64_t orc_alloc(void* h, int64_t size) { return static_cast<Heap*>(h)->alloc(size); }
+int orc_dealloc(void* h, int64_t off) { return static_cast<Heap*>(h)->dealloc(off); }
+int64_t orc_dump(void* h, int64_t* buf, int64_t cap) {
+    return copy_state(*static_cast<Heap*>(h), buf, cap);
+}
+void orc_stats(void* h, uint64_t* out2) {
+    out2[0] = static_cast<Heap*>(h)->examined;
+    out2[1] = static_cast<Heap*>(h)->touched;
+}
+// Replay request i in order on heap h (same driver as orc_replay).
+void orc_replay_on(void* h, int64_t n, const int64_t* req, int64_t* res) {
+    replay_one(*static_cast<Heap*>(h), n, req, res);
+}
+
+// Replay a CSR batch of heaps on `threads` host threads (heaps are split
+// longest-first over the threads).  state/state_off may be null; otherwise
+// heap i's state is written at state + state_off[i] with capacity
+// state_off[i+1]-state_off[i] and its length (in words) to state_len[i].
+// stats (may be null) receives per-heap {examined, touched}.
+int orc_replay_batch(int64_t H, const int64_t* arena, const int64_t* align,
+                     const int32_t* algo, const int64_t* req_off, const int64_t* req,
+                     int64_t* res, int64_t* state, const int64_t* state_off,
+                     int64_t* state_len, uint64_t* stats, int threads) {
+    for (int64_t i = 0; i < H; ++i)
+        if (!valid_params(algo[i], arena[i], align[i])) return E_INVAL;
+    std::vector<int64_t> order(H);
+    for (int64_t i = 0; i < H; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+        return req_off[a + 1] - req_off[a] > req_off[b + 1] - req_off[b];
+    });
+    if (threads < 1) threads = 1;
+    std::vector<std::vector<int64_t>> part(threads);
+    std::vector<int64_t> load(threads, 0);
+    for (int64_t i : order) {                 // longest-processing-time first
+        int t = int(std::min_element(load.begin(), load.end()) - load.begin());
+        part[t].push_back(i);
+        load[t] += req_off[i + 1] - req_off[i];
+    }
+    auto work = [&](int t) {
+        for (int64_t i : part[t]) {
+            Heap h(algo[i], arena[i], align[i]);
+            replay_one(h, req_off[i + 1] - req_off[i], req + req_off[i], res + req_off[i]);
+            if (state)
+                state_len[i] = copy_state(h, state + state_off[i], state_off[i + 1] - state_off[i]);
+            if (stats) { stats[2 * i] = h.examined; stats[2 * i + 1] = h.touched; }
+        }
+    };
+    if (threads == 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> th;
+        for (int t = 0; t < threads; ++t) th.emplace_back(work, t);
+        for (auto& x : th) x.join();
+    }
+    return 0;
+}
+
+}  // extern "C"

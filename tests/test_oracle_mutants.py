@@ -1,0 +1,94 @@
+"""Planted mistakes in the oracle must be caught by its pins.
+
+Each case copies the oracle source, applies one plausible slip (a dropped
+term, a wrong comparison, a wrong index, a missed bookkeeping step), builds it
+on the CPU and runs the pin suite against that build.  The suite has to fail
+for every mutant."""
+import os
+import subprocess
+import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "hda_oracle.cpp")
+
+# (name, text, replacement, occurrence)
+MUTANTS = [
+    ("ff_strict_fit", "if (it->second >= s) { pick = it; break; }",
+     "if (it->second > s) { pick = it; break; }", 0),
+    ("nf_strict_fit", "if (it->second >= s) { pick = it; break; }",
+     "if (it->second > s) { pick = it; break; }", 1),
+    ("bf_tie_highest_address", "it->second < pick->second", "it->second <= pick->second", 0),
+    ("nf_start_rule", "start->first + start->second <= rover",
+     "start->first + start->second < rover", 0),
+    ("nf_rover_at_start", "rover = a + s;", "rover = a;", 0),
+    ("split_size_dropped", "fl[a + s] = bsize - s;", "fl[a + s] = bsize;", 0),
+    ("three_way_merge_drops_right", "pred->second += s + succ->second;",
+     "pred->second += s;", 0),
+    ("right_merge_drops_size", "fl[x] = s + sz;", "fl[x] = s;", 0),
+    ("right_adjacency_index", "succ->first == x + s", "succ->first == x", 0),
+    ("sf_request_class_floor", "int k = ceil_log2(uint64_t(s));",
+     "int k = floor_log2(uint64_t(s));", 0),
+    ("sf_highest_class", "int c = __builtin_ctzll(m);", "int c = 63 - __builtin_clzll(m);", 0),
+    ("sf_bit_not_cleared", "if (head[c] == NIL) bitmap &= ~(uint64_t(1) << c);", "", 0),
+    ("sf_push_class_ceil", "int c = floor_log2(uint64_t(r.size));\n        r.prev_free = NIL;",
+     "int c = ceil_log2(uint64_t(r.size));\n        r.prev_free = NIL;", 0),
+    ("sf_unlink_drops_tail", "else head[c] = r.next_free;", "else head[c] = NIL;", 0),
+    # (Writing l instead of l's own left link into the merged record is NOT a
+    # mistake the state can show: that link is rewritten before it is ever read
+    # while the left neighbour is free, so it is not listed.)
+    ("sf_merge_right_link_not_fixed", "if (end < A) { ht.at(end).prev_adj = start; ++touched; }",
+     "", 0),
+    ("sf_split_prev_adj_not_fixed", "if (old_end < A) { ht.at(old_end).prev_adj = b; ++touched; }",
+     "", 0),
+    ("driver_modulo_index", "uint64_t idx = (r * uint64_t(h.live.size())) >> 32;",
+     "uint64_t idx = r % uint64_t(h.live.size());", 0),
+    ("driver_no_swap", "*lv = live.back();\n        live.pop_back();", "live.erase(lv);", 0),
+    ("size_not_rounded", "int64_t s = (req + g - 1) / g * g;", "int64_t s = req;", 0),
+]
+
+PINS = os.path.join(ROOT, "tests", "test_oracle_pins.py")
+
+
+def _replace_nth(text, old, new, n):
+    idx = -1
+    for _ in range(n + 1):
+        idx = text.find(old, idx + 1)
+        assert idx >= 0, f"mutation anchor not found: {old!r}"
+    return text[:idx] + new + text[idx + len(old):]
+
+
+def _run(m, tmp):
+    name, old, new, n = m
+    src = open(SRC).read()
+    mutated = _replace_nth(src, old, new, n)
+    assert mutated != src
+    cpp = os.path.join(tmp, f"{name}.cpp")
+    so = os.path.join(tmp, f"{name}.so")
+    with open(cpp, "w") as f:
+        f.write(mutated)
+    subprocess.check_call(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-pthread",
+                           cpp, "-o", so])
+    env = dict(os.environ, HDA_ORACLE_LIB=so)
+    p = subprocess.run([sys.executable, "-m", "pytest", PINS, "-x", "-q",
+                        "-p", "no:cacheprovider", "--timeout", "120",
+                        "-k", "not depth6"],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+    return name, p.returncode
+
+
+def test_every_anchor_is_unique_enough():
+    src = open(SRC).read()
+    for name, old, _, n in MUTANTS:
+        assert src.count(old) > n, name
+
+
+def test_pins_catch_planted_mistakes():
+    with tempfile.TemporaryDirectory() as tmp:
+        with ThreadPoolExecutor(4) as ex:
+            results = list(ex.map(lambda m: _run(m, tmp), MUTANTS))
+    survivors = [name for name, rc in results if rc == 0]
+    assert not survivors, f"pins did not catch: {survivors}"
