@@ -1,0 +1,46 @@
+// Wavefront primitives for gfx950 (64 lanes): lane id, ballot, readlane,
+// readfirstlane, DPP row shift and ds_bpermute.  hda_core.h is written only
+// against these names, so the same core can be compiled elsewhere with
+// another definition of them (the test-suite runs it on the CPU with a
+// lockstep emulation of a wave).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// Pointers into LDS keep their address space, so accesses through them are
+// ds_* instructions rather than generic (FLAT) ones.
+#define HDA_LDS __attribute__((address_space(3)))
+#define HDA_GLOBAL __attribute__((address_space(1)))
+
+namespace hda {
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+
+__device__ __forceinline__ uint64_t ballot(bool p) {
+  return __builtin_amdgcn_ballot_w64(p);
+}
+
+__device__ __forceinline__ uint32_t rdlane(uint32_t v, uint32_t l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// Lane i of each 16-lane row receives src from lane i-K of the same row;
+// lanes with no such source receive `old`.
+template <int K>
+__device__ __forceinline__ uint32_t row_shr(uint32_t old, uint32_t src) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x110 + K, 0xf, 0xf, false);
+}
+
+__device__ __forceinline__ uint32_t shfl(uint32_t v, uint32_t src_lane) {
+  return (uint32_t)__shfl((int)v, (int)src_lane);
+}
+
+// Ordering point between table accesses; lanes of a wave already execute in
+// lockstep on the hardware, so there is nothing to do here.
+__device__ __forceinline__ void wave_sync() {}
+
+}  // namespace hda

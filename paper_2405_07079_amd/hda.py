@@ -1,0 +1,272 @@
+"""ctypes binding of ``libhda.so`` (the gfx950 library declared in
+``include/hda.h``).  Argument marshalling only: every allocator step runs in
+the library's kernels.  PyTorch provides the device buffers and the stream.
+
+Importing this module does not load the library; the first call does, and it
+raises if ``libhda.so`` has not been built -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhda.so")
+
+FIRST_FIT, NEXT_FIT, BEST_FIT, SEG_FIT = 0, 1, 2, 3
+HDA_OK, HDA_FAIL, HDA_E_INVAL, HDA_E_BADFREE = 0, -1, -2, -3
+HDA_E_NOMETA, HDA_E_DEVICE, HDA_E_BUSY, HDA_E_RANGE = -4, -5, -6, -7
+
+
+class HdaError(RuntimeError):
+    def __init__(self, code, what=""):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+class hda_tuning(ctypes.Structure):
+    _fields_ = [("heaps_per_group", ctypes.c_int32), ("lds_free", ctypes.c_int32),
+                ("lds_live", ctypes.c_int32), ("groups", ctypes.c_int32)]
+
+
+class hda_batch_desc(ctypes.Structure):
+    _fields_ = [("n_heaps", ctypes.c_int64),
+                ("arena", ctypes.c_void_p), ("align", ctypes.c_void_p),
+                ("algo", ctypes.c_void_p), ("req_off", ctypes.c_void_p),
+                ("req", ctypes.c_void_p), ("res", ctypes.c_void_p),
+                ("order", ctypes.c_void_p), ("state", ctypes.c_void_p),
+                ("state_off", ctypes.c_void_p), ("state_len", ctypes.c_void_p),
+                ("status", ctypes.c_void_p),
+                ("meta_free", ctypes.c_int64), ("meta_live", ctypes.c_int64),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("tuning", hda_tuning)]
+
+
+_lib = None
+
+EXPORTS = ["hda_replay_workspace", "hda_replay_resolve", "hda_replay",
+           "hda_replay_per_heap", "hda_heap_create", "hda_heap_destroy", "hda_alloc",
+           "hda_free", "hda_heap_state", "hda_set_meta_budget", "hda_strerror"]
+
+
+def lib():
+    """Load libhda.so (raises if it is missing: build it first)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run paper_2405_07079_amd/build.py "
+                               "(the GPU library has no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        D = ctypes.POINTER(hda_batch_desc)
+        L.hda_replay_workspace.restype = ctypes.c_size_t
+        L.hda_replay_workspace.argtypes = [D]
+        L.hda_replay_resolve.restype = ctypes.c_int
+        L.hda_replay_resolve.argtypes = [D, ctypes.POINTER(hda_tuning)]
+        L.hda_replay.restype = ctypes.c_int
+        L.hda_replay.argtypes = [D, vp]
+        L.hda_replay_per_heap.restype = ctypes.c_int
+        L.hda_replay_per_heap.argtypes = [D, vp]
+        L.hda_heap_create.restype = ctypes.c_int
+        L.hda_heap_create.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
+                                      ctypes.c_uint32, ctypes.POINTER(vp)]
+        L.hda_heap_destroy.restype = ctypes.c_int
+        L.hda_heap_destroy.argtypes = [vp]
+        L.hda_alloc.restype = ctypes.c_int64
+        L.hda_alloc.argtypes = [vp, ctypes.c_uint64]
+        L.hda_free.restype = ctypes.c_int
+        L.hda_free.argtypes = [vp, ctypes.c_int64]
+        L.hda_heap_state.restype = ctypes.c_int
+        L.hda_heap_state.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+        L.hda_set_meta_budget.restype = ctypes.c_int64
+        L.hda_set_meta_budget.argtypes = [ctypes.c_int64]
+        L.hda_strerror.restype = ctypes.c_char_p
+        L.hda_strerror.argtypes = [ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    try:
+        return lib().hda_strerror(int(code)).decode()
+    except Exception:  # library not loadable: still give a readable message
+        return f"error {code}"
+
+
+def _check(code, what):
+    if code != HDA_OK:
+        raise HdaError(code, what)
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# Batched replay
+# ---------------------------------------------------------------------------
+
+@dataclass
+class DeviceBatch:
+    """A workloads.Batch resident in device memory, with output buffers."""
+    n_heaps: int
+    arena: "torch.Tensor"
+    align: "torch.Tensor"
+    algo: "torch.Tensor"
+    req_off: "torch.Tensor"
+    req: "torch.Tensor"
+    res: "torch.Tensor"
+    order: "torch.Tensor | None"
+    state: "torch.Tensor | None"
+    state_off: "torch.Tensor | None"
+    state_len: "torch.Tensor | None"
+    status: "torch.Tensor"
+    meta_free: int
+    meta_live: int
+    workspace: "torch.Tensor | None" = None
+    tuning: tuple = (0, 0, 0, 0)
+
+    def desc(self) -> hda_batch_desc:
+        d = hda_batch_desc()
+        p = lambda t: None if t is None else t.data_ptr()  # noqa: E731
+        d.n_heaps = self.n_heaps
+        d.arena, d.align, d.algo = p(self.arena), p(self.align), p(self.algo)
+        d.req_off, d.req, d.res = p(self.req_off), p(self.req), p(self.res)
+        d.order = p(self.order)
+        d.state, d.state_off, d.state_len = p(self.state), p(self.state_off), p(self.state_len)
+        d.status = p(self.status)
+        d.meta_free, d.meta_live = self.meta_free, self.meta_live
+        d.workspace = p(self.workspace)
+        d.workspace_bytes = 0 if self.workspace is None else self.workspace.numel()
+        d.tuning = hda_tuning(*self.tuning)
+        return d
+
+
+def state_words(algo, blocks):
+    """Words of a canonical state dump with at most `blocks` free + live blocks."""
+    algo = np.asarray(algo)
+    blocks = np.asarray(blocks, dtype=np.int64)
+    return 4 + 2 * blocks + np.where(algo == SEG_FIT, 64 + blocks, 0)
+
+
+def upload(batch, device="cuda", order="lpt", with_state=True, meta_free=4096,
+           meta_live=8192, tuning=(0, 0, 0, 0)) -> DeviceBatch:
+    """Copy a workloads.Batch to the device and allocate results, states,
+    status and the library's workspace (all torch-owned)."""
+    import torch
+    H = batch.heaps
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dt)).to(device)  # noqa: E731
+    lens = np.diff(batch.req_off)
+    if order == "lpt":      # longest trace first; ties keep heap order
+        ordv = np.argsort(-lens, kind="stable").astype(np.int32)
+        order_t = t(ordv, np.int32)
+    elif order is None:
+        order_t = None
+    else:
+        order_t = t(order, np.int32)
+    state = state_off = state_len = None
+    if with_state:
+        blocks = np.minimum(lens + 1, meta_free + meta_live)
+        caps = state_words(batch.algo, blocks).astype(np.int64)
+        so = np.zeros(H + 1, np.int64)
+        np.cumsum(caps, out=so[1:])
+        state = torch.empty(int(so[-1]), dtype=torch.int64, device=device)
+        state_off = t(so, np.int64)
+        state_len = torch.zeros(H, dtype=torch.int64, device=device)
+    db = DeviceBatch(H, t(batch.arena, np.int64), t(batch.align, np.int64),
+                     t(batch.algo, np.int32), t(batch.req_off, np.int64),
+                     t(batch.req, np.int64),
+                     torch.empty(batch.requests, dtype=torch.int64, device=device),
+                     order_t, state, state_off, state_len,
+                     torch.zeros(H, dtype=torch.int32, device=device),
+                     int(meta_free), int(meta_live), None, tuple(tuning))
+    ws = hda_replay_workspace(db)
+    db.workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=device)
+    return db
+
+
+def hda_replay_workspace(db: DeviceBatch) -> int:
+    n = lib().hda_replay_workspace(ctypes.byref(db.desc()))
+    if n == 0:
+        raise HdaError(HDA_E_INVAL, "hda_replay_workspace")
+    return int(n)
+
+
+def hda_replay_resolve(db: DeviceBatch) -> tuple:
+    out = hda_tuning()
+    _check(lib().hda_replay_resolve(ctypes.byref(db.desc()), ctypes.byref(out)),
+           "hda_replay_resolve")
+    return (out.heaps_per_group, out.lds_free, out.lds_live, out.groups)
+
+
+def hda_replay(db: DeviceBatch, stream=None) -> None:
+    """Enqueue the batched replay on `stream` (default: torch's current)."""
+    _check(lib().hda_replay(ctypes.byref(db.desc()), _stream_ptr(stream)), "hda_replay")
+
+
+def hda_replay_per_heap(db: DeviceBatch, stream=None) -> None:
+    """Enqueue one launch per heap (the per-heap baseline) on `stream`."""
+    _check(lib().hda_replay_per_heap(ctypes.byref(db.desc()), _stream_ptr(stream)),
+           "hda_replay_per_heap")
+
+
+def states_to_host(db: DeviceBatch, heaps=None):
+    """Per-heap canonical states as numpy arrays (a list; heaps=None: all)."""
+    so = db.state_off.cpu().numpy()
+    sl = db.state_len.cpu().numpy()
+    heaps = range(db.n_heaps) if heaps is None else heaps
+    out = []
+    for h in heaps:
+        n = min(int(sl[h]), int(so[h + 1] - so[h]))
+        out.append(db.state[int(so[h]):int(so[h]) + n].cpu().numpy())
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Single heaps, call by call
+# ---------------------------------------------------------------------------
+
+class Heap:
+    """A device-resident heap driven call by call (synchronous calls)."""
+
+    def __init__(self, arena: int, align: int, algo: int, meta_cap: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().hda_heap_create(int(arena), int(align), int(algo), int(meta_cap),
+                                     ctypes.byref(h)), "hda_heap_create")
+        self._h = h
+        self.algo = int(algo)
+
+    def close(self):
+        if self._h:
+            _check(lib().hda_heap_destroy(self._h), "hda_heap_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def alloc(self, size: int) -> int:
+        r = int(lib().hda_alloc(self._h, int(size)))
+        if r < -1:
+            raise HdaError(r, "hda_alloc")
+        return r
+
+    def free(self, offset: int) -> int:
+        return int(lib().hda_free(self._h, int(offset)))
+
+    def state(self) -> np.ndarray:
+        n = ctypes.c_size_t(0)
+        rc = lib().hda_heap_state(self._h, None, 0, ctypes.byref(n))
+        if rc not in (HDA_OK, HDA_E_RANGE):
+            raise HdaError(rc, "hda_heap_state")
+        buf = np.empty(n.value, np.int64)
+        _check(lib().hda_heap_state(self._h, buf.ctypes.data, n.value, ctypes.byref(n)),
+               "hda_heap_state")
+        return buf

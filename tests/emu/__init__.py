@@ -1,0 +1,57 @@
+"""Build and run the device replay core under the CPU lockstep wave
+emulation (test infrastructure)."""
+import ctypes
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+CSRC = os.path.join(ROOT, "paper_2405_07079_amd", "csrc")
+_lib = None
+
+
+def build():
+    out = os.path.join(tempfile.gettempdir(), f"hda_emu_{os.getpid()}.so")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC",
+                           "-I", HERE, "-I", CSRC, os.path.join(HERE, "emu_replay.cpp"),
+                           "-o", out])
+    return out
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = ctypes.CDLL(build())
+        vp = ctypes.c_void_p
+        u32 = ctypes.c_uint32
+        L.emu_replay.restype = ctypes.c_int
+        L.emu_replay.argtypes = [ctypes.c_int64] + [vp] * 10 + [u32] * 4 + [vp]
+        _lib = L
+    return _lib
+
+
+def replay(batch, kf=64, kl=64, cf=4096, cl=4096):
+    """Replay a workloads.Batch heap by heap in the emulator."""
+    H = batch.heaps
+    P = lambda a: a.ctypes.data  # noqa: E731
+    arena = np.ascontiguousarray(batch.arena, np.int64)
+    align = np.ascontiguousarray(batch.align, np.int64)
+    algo = np.ascontiguousarray(batch.algo, np.int32)
+    off = np.ascontiguousarray(batch.req_off, np.int64)
+    req = np.ascontiguousarray(batch.req, np.int64)
+    res = np.full(req.shape, 0x7777, np.int64)
+    lens = np.diff(off)
+    caps = 4 + 2 * (lens + 1) + np.where(algo == 3, 64 + lens + 1, 0)
+    so = np.zeros(H + 1, np.int64)
+    np.cumsum(caps, out=so[1:])
+    state = np.zeros(int(so[-1]), np.int64)
+    sl = np.zeros(H, np.int64)
+    status = np.zeros(H, np.int32)
+    syncs = np.zeros(H, np.uint64)
+    lib().emu_replay(H, P(arena), P(align), P(algo), P(off), P(req), P(res), P(state),
+                     P(so), P(sl), P(status), kf, kl, cf, cl, P(syncs))
+    states = [state[so[h]:so[h] + sl[h]].copy() for h in range(H)]
+    return res, states, status, syncs

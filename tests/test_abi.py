@@ -1,0 +1,37 @@
+"""The C-ABI library loads on a machine without a GPU and exports every entry
+point that include/hda.h declares (no compute calls here)."""
+import ctypes
+import os
+import re
+
+from paper_2405_07079_amd import hda
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    text = open(os.path.join(ROOT, "include", "hda.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hda_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ("hda_heap_create", "hda_alloc", "hda_free", "hda_heap_destroy",
+              "hda_replay", "hda_heap_state"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(hda.LIB_PATH)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_knows_every_symbol():
+    assert sorted(hda.EXPORTS) == declared()
+
+
+def test_strerror_without_gpu():
+    assert hda.strerror(hda.HDA_E_BADFREE).startswith("free of an offset")
+    assert hda.strerror(12345) == "unknown error"

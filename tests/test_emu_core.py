@@ -1,0 +1,91 @@
+"""The device replay core, compiled for the CPU and run as a lockstep-emulated
+wavefront (tests/emu), against the oracle.  This checks the kernel's own
+logic (selection by wave reductions, swap-remove tables, push stamps, LDS /
+spill split, capacity errors, state dump) without a GPU."""
+import numpy as np
+import pytest
+
+import emu
+import oracle
+from paper_2405_07079_amd import workloads as W
+
+ALGOS = (0, 1, 2, 3)
+
+
+def check(batch, res, states, status, heaps=None):
+    heaps = list(range(batch.heaps)) if heaps is None else list(heaps)
+    sub = batch.subset(heaps)
+    ores, ostates, _ = oracle.replay_batch(sub)
+    for k, h in enumerate(heaps):
+        a, b = batch.req_off[h], batch.req_off[h + 1]
+        got, exp = res[a:b], ores[sub.req_off[k]:sub.req_off[k + 1]]
+        if not np.array_equal(got, exp):
+            i = int(np.nonzero(got != exp)[0][0])
+            raise AssertionError(f"heap {h} algo {batch.algo[h]} request {i}: "
+                                 f"emulated {got[i]} oracle {exp[i]}")
+        assert status[h] == 0
+        assert np.array_equal(states[h], ostates[k]), f"heap {h} state"
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_single_heap_64KiB_default_tables(algo):
+    b = W.single_heap(n=4000).with_algo(algo)
+    res, states, status, _ = emu.replay(b, kf=256, kl=768, cf=4096, cl=8192)
+    check(b, res, states, status)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_single_heap_spilling_tables(algo):
+    b = W.single_heap(n=3000, seed=7).with_algo(algo)
+    res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=4096, cl=4096)
+    check(b, res, states, status)
+
+
+def test_random_small_heaps():
+    rng = np.random.default_rng(5)
+    parts = []
+    for h in range(40):
+        gran = int(rng.integers(1, 120))
+        parts.append(W.random_tiny(int(rng.integers(1 << 30)), int(rng.integers(0, 300)),
+                                   gran, align=int(1 << rng.integers(0, 12)),
+                                   algo=int(rng.integers(0, 4)),
+                                   max_granules=max(1, gran // int(rng.integers(1, 6)))))
+    b = W.concat(parts)
+    res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=512, cl=512)
+    check(b, res, states, status)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_16MiB_heap(algo):
+    b = W.uniform_batch(heaps=1, n=2500, algo=algo)
+    res, states, status, _ = emu.replay(b, kf=128, kl=128, cf=4096, cl=4096)
+    check(b, res, states, status)
+
+
+def test_capacity_exhausted_changes_nothing():
+    b = W.uniform_batch(heaps=1, n=1500, algo=2)
+    res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=64, cl=64)
+    ores, _, _ = oracle.replay_batch(b, want_state=False)
+    assert status[0] == -4
+    first = int(np.nonzero(res == -4)[0][0])
+    assert np.array_equal(res[:first], ores[:first])
+    st = oracle.parse_state(states[0], 2)
+    assert len(st["live"]) <= 64 and len(st["free"]) <= 64
+    # a request refused for capacity leaves the state as it was: replaying the
+    # accepted requests alone on the oracle gives the same final state
+    acc = b.req[res != -4]
+    h = oracle.Heap(2, int(b.arena[0]), int(b.align[0]))
+    keep = h.replay(acc)
+    assert np.array_equal(keep, res[res != -4])
+    assert np.array_equal(h.state(), states[0])
+
+
+def test_invalid_heap_parameters():
+    good = W.random_tiny(1, 50, 32, align=16)
+    bad = W.random_tiny(2, 40, 8, align=16)
+    bad.arena[:] = 1000
+    b = W.concat([good, bad, good])
+    res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=256, cl=256)
+    assert status.tolist() == [0, -2, 0]
+    assert (res[b.req_off[1]:b.req_off[2]] == -2).all()
+    check(b, res, states, status, heaps=[0, 2])

@@ -1,0 +1,78 @@
+"""Call-by-call heaps on the GPU (hda_heap_create / hda_alloc / hda_free /
+hda_heap_state) against oracle heaps driven with the same calls."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_07079_amd import hda
+
+pytestmark = pytest.mark.gpu
+pytest.importorskip("torch")
+
+
+@pytest.mark.parametrize("algo", (0, 1, 2, 3))
+def test_calls_match_oracle(algo):
+    print(f"case: call-by-call heap algo {algo}", flush=True)
+    A, g = 1 << 16, 32
+    gh = hda.Heap(A, g, algo, meta_cap=512)
+    oh = oracle.Heap(algo, A, g)
+    rng = np.random.default_rng(algo)
+    live = []
+    for step in range(300):
+        if live and rng.random() < 0.45:
+            x = live.pop(int(rng.integers(len(live))))
+            assert gh.free(x) == oh.free(x) == 0
+        else:
+            size = int(rng.integers(0, 3000))
+            r = gh.alloc(size)
+            assert r == oh.alloc(size), step
+            if r >= 0:
+                live.append(r)
+        if step % 50 == 0:
+            assert np.array_equal(gh.state(), oh.state())
+    assert np.array_equal(gh.state(), oh.state())
+    gh.close()
+
+
+@pytest.mark.parametrize("algo", (0, 3))
+def test_bad_and_double_free(algo):
+    print(f"case: bad free algo {algo}", flush=True)
+    gh = hda.Heap(4096, 16, algo)
+    a = gh.alloc(100)
+    gh.alloc(100)
+    before = gh.state()
+    assert gh.free(a + 16) == hda.HDA_E_BADFREE
+    assert gh.free(-16) == hda.HDA_E_BADFREE
+    assert gh.free(1 << 20) == hda.HDA_E_BADFREE
+    assert np.array_equal(gh.state(), before)
+    assert gh.free(a) == 0
+    after = gh.state()
+    assert gh.free(a) == hda.HDA_E_BADFREE
+    assert np.array_equal(gh.state(), after)
+
+
+def test_create_rejects_bad_arguments():
+    for A, g, algo in ((1000, 16, 0), (1024, 24, 0), (1024, 16, 9), (0, 16, 0),
+                       (1 << 40, 16, 0)):
+        with pytest.raises(hda.HdaError) as e:
+            hda.Heap(A, g, algo)
+        assert e.value.code == hda.HDA_E_INVAL
+
+
+def test_metadata_budget_admission():
+    print("case: metadata budget", flush=True)
+    held0 = hda.lib().hda_set_meta_budget(0)
+    one = hda.Heap(1 << 20, 64, 3, meta_cap=256)
+    per_heap = hda.lib().hda_set_meta_budget(0) - held0
+    assert per_heap > 0
+    hda.lib().hda_set_meta_budget(held0 + 2 * per_heap)
+    two = hda.Heap(1 << 20, 64, 3, meta_cap=256)
+    with pytest.raises(hda.HdaError) as e:
+        hda.Heap(1 << 20, 64, 3, meta_cap=256)
+    assert e.value.code == hda.HDA_E_NOMETA
+    one.close()                                   # releases budget
+    three = hda.Heap(1 << 20, 64, 3, meta_cap=256)
+    assert three.alloc(1000) == 0
+    hda.lib().hda_set_meta_budget(0)
+    two.close()
+    three.close()

@@ -1,0 +1,197 @@
+"""GPU batched replay vs the CPU oracle, element by element (integers: exact).
+
+Every test calls the library through its C ABI (the ctypes binding)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_07079_amd import hda
+from paper_2405_07079_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+ALGOS = (0, 1, 2, 3)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def gpu_replay(batch, tuning=(0, 0, 0, 0), meta_free=4096, meta_live=8192,
+               per_heap=False, order="lpt", with_state=True):
+    db = hda.upload(batch, order=order, tuning=tuning, meta_free=meta_free,
+                    meta_live=meta_live, with_state=with_state)
+    (hda.hda_replay_per_heap if per_heap else hda.hda_replay)(db)
+    torch.cuda.synchronize()
+    states = hda.states_to_host(db) if with_state else None
+    return db.res.cpu().numpy(), states, db.status.cpu().numpy()
+
+
+def check_against_oracle(batch, res, states, status, heaps=None):
+    heaps = list(range(batch.heaps)) if heaps is None else list(heaps)
+    sub = batch.subset(heaps)
+    ores, ostates, _ = oracle.replay_batch(sub, threads=8)
+    for k, h in enumerate(heaps):
+        a, b = batch.req_off[h], batch.req_off[h + 1]
+        got = res[a:b]
+        exp = ores[sub.req_off[k]:sub.req_off[k + 1]]
+        if not np.array_equal(got, exp):
+            bad = int(np.nonzero(got != exp)[0][0])
+            raise AssertionError(f"heap {h} (algo {batch.algo[h]}) request {bad}: "
+                                 f"gpu {got[bad]} oracle {exp[bad]} req {batch.req[a + bad]}")
+        assert status[h] == 0, (h, status[h])
+        if states is not None:
+            assert np.array_equal(states[h], ostates[k]), f"heap {h} state differs"
+
+
+def test_single_heap_64KiB_all_algorithms():
+    base = W.single_heap()
+    b = W.concat([base.with_algo(a) for a in ALGOS], "single_heap x4")
+    say("case: single heap 64 KiB, 10k requests, algos", ALGOS)
+    res, states, status = gpu_replay(b)
+    check_against_oracle(b, res, states, status)
+
+
+def random_small_batch(seed, heaps, max_len=1500):
+    rng = np.random.default_rng(seed)
+    parts = []
+    for h in range(heaps):
+        gran = int(rng.integers(1, 300))
+        align = int(1 << rng.integers(0, 13))
+        n = int(rng.integers(0, max_len)) if h % 17 else 0
+        algo = int(rng.integers(0, 4))
+        parts.append(W.random_tiny(int(rng.integers(1 << 30)), n, gran, align=align,
+                                   p_alloc=float(rng.uniform(0.4, 0.75)), algo=algo,
+                                   max_granules=max(1, gran // int(rng.integers(1, 8)))))
+    return W.concat(parts, "random_small")
+
+
+def test_random_small_heaps_mixed():
+    b = random_small_batch(11, 600)
+    say("case: 600 random small heaps, mixed algorithms/alignments, some empty")
+    res, states, status = gpu_replay(b)
+    check_against_oracle(b, res, states, status)
+
+
+def c2_like(heaps, n, algo):
+    return W.uniform_batch(seed=2, heaps=heaps, n=n, algo=algo)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_16MiB_heaps_reduced(algo):
+    b = c2_like(48, 30_000, algo)
+    say(f"case: 48 x 16 MiB heaps, 30k requests, algo {algo}, default tuning")
+    res, states, status = gpu_replay(b)
+    check_against_oracle(b, res, states, status)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_spill_to_device_memory(algo):
+    """Only 64 free and 64 live entries in LDS: most of each table spills."""
+    b = c2_like(24, 20_000, algo)
+    say(f"case: 24 x 16 MiB heaps, 20k requests, algo {algo}, lds 64/64")
+    res, states, status = gpu_replay(b, tuning=(2, 64, 64, 0))
+    check_against_oracle(b, res, states, status)
+
+
+def test_tuning_does_not_change_results():
+    b = W.concat([c2_like(16, 8000, a) for a in ALGOS], "mixed")
+    ref = None
+    for tu in ((0, 0, 0, 0), (1, 64, 64, 0), (8, 128, 256, 0), (16, 64, 512, 3), (2, 512, 1024, 1)):
+        say("case: tuning", tu)
+        res, states, status = gpu_replay(b, tuning=tu)
+        assert (status == 0).all()
+        if ref is None:
+            ref = (res, states)
+            check_against_oracle(b, res, states, status)
+        else:
+            assert np.array_equal(res, ref[0])
+            assert all(np.array_equal(x, y) for x, y in zip(states, ref[1]))
+
+
+def test_per_heap_launch_matches_batched():
+    b = W.concat([c2_like(6, 5000, a) for a in ALGOS], "mixed")
+    say("case: per-heap launches, 24 heaps")
+    r1, s1, st1 = gpu_replay(b)
+    r2, s2, st2 = gpu_replay(b, per_heap=True)
+    assert np.array_equal(r1, r2)
+    assert all(np.array_equal(x, y) for x, y in zip(s1, s2))
+    check_against_oracle(b, r2, s2, st2)
+
+
+def test_uneven_batch_reduced():
+    b = W.uneven_batch(heaps=2048, len_scale=0.02)
+    say(f"case: uneven batch 2048 heaps, {b.requests} requests")
+    res, states, status = gpu_replay(b)
+    rng = np.random.default_rng(0)
+    lens = np.diff(b.req_off)
+    heaps = sorted(set(rng.choice(b.heaps, 200, replace=False).tolist())
+                   | set(np.argsort(-lens)[:8].tolist()))
+    check_against_oracle(b, res, states, status, heaps)
+
+
+def test_bad_heap_parameters():
+    good = W.random_tiny(1, 50, 32, align=16)
+    bad = []
+    for A, g, algo in ((1000, 16, 0), (1024, 24, 0), (1024, 16, 7), (0, 16, 1),
+                       (1 << 40, 16, 2)):
+        b = W.random_tiny(2, 40, 8, align=16)
+        b.arena[:] = A
+        b.align[:] = g
+        b.algo[:] = algo
+        bad.append(b)
+    batch = W.concat([good] + bad + [good], "bad")
+    say("case: heaps with invalid parameters")
+    res, states, status = gpu_replay(batch)
+    assert status.tolist() == [0, -2, -2, -2, -2, -2, 0]
+    for h in range(1, 6):
+        a, b_ = batch.req_off[h], batch.req_off[h + 1]
+        assert (res[a:b_] == hda.HDA_E_INVAL).all()
+    check_against_oracle(batch, res, states, status, [0, 6])
+
+
+def test_state_slot_too_small():
+    b = c2_like(2, 3000, 3)
+    db = hda.upload(b)
+    so = db.state_off.cpu().numpy()
+    so[1] = so[0] + 10          # heap 0 gets a 10-word slot
+    db.state_off = torch.from_numpy(so).cuda()
+    say("case: state slot too small")
+    hda.hda_replay(db)
+    torch.cuda.synchronize()
+    st = db.status.cpu().numpy()
+    assert st[0] == hda.HDA_E_RANGE and st[1] == 0
+    need = int(db.state_len[0].item())
+    _, ostates, _ = oracle.replay_batch(b.subset([0]))
+    assert need == len(ostates[0])
+
+
+def test_metadata_capacity_exhausted():
+    """A heap whose live set outgrows its table gets HDA_E_NOMETA for the
+    requests that would need a new entry; earlier results are unaffected."""
+    b = c2_like(2, 4000, 2)
+    say("case: live-table capacity 64")
+    res, states, status = gpu_replay(b, tuning=(1, 64, 64, 0), meta_free=64, meta_live=64)
+    ores, _, _ = oracle.replay_batch(b, want_state=False)
+    assert (status == hda.HDA_E_NOMETA).all()
+    for h in range(2):
+        a, e = b.req_off[h], b.req_off[h + 1]
+        first = int(np.nonzero(res[a:e] == hda.HDA_E_NOMETA)[0][0])
+        assert np.array_equal(res[a:a + first], ores[a:a + first])
+        # the live table never exceeds its capacity
+        st = oracle.parse_state(states[h], 2)
+        assert len(st["live"]) <= 64 and len(st["free"]) <= 64
+
+
+def test_empty_batch_and_empty_heaps():
+    b = W.random_tiny(3, 0, 16)
+    say("case: empty traces")
+    res, states, status = gpu_replay(W.concat([b, b, b]))
+    assert res.size == 0 and (status == 0).all()
+    st = oracle.parse_state(states[0], 0)
+    assert st["free"] == [(0, 256)] and st["live"] == []
+    db = hda.upload(W.concat([b]))
+    db.n_heaps = 0
+    hda.hda_replay(db)
+    torch.cuda.synchronize()
