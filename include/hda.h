@@ -76,11 +76,18 @@ enum {
  *   segregated fit only: for each class k = 0..63 (sizes in [2^k, 2^(k+1))):
  *     len_k, then the block addresses from list head to tail.
  */
+/* Where each heap's tables live.  The first 64*reg_free free entries and
+ * 64*reg_live live entries are held in vector registers, the next lds_free /
+ * lds_live entries in LDS, and the rest (up to the capacities) in device
+ * memory.  0 = default for every field; -1 = none of that storage.  Register
+ * shapes compiled in: (reg_free, reg_live) = (-1,-1), (4,8), (6,12), (8,16). */
 typedef struct hda_tuning {
-  int32_t heaps_per_group; /* waves (= heaps in flight) per workgroup; 0 = auto */
-  int32_t lds_free;        /* free-table entries kept in LDS per heap (mult. of 64); 0 = auto */
-  int32_t lds_live;        /* live-table entries kept in LDS per heap (mult. of 64); 0 = auto */
-  int32_t groups;          /* persistent workgroups; 0 = fill the device       */
+  int32_t heaps_per_group; /* waves (= heaps in flight) per workgroup (1..16)  */
+  int32_t reg_free;        /* free-table 64-entry chunks in registers          */
+  int32_t reg_live;        /* live-table 64-entry chunks in registers          */
+  int32_t lds_free;        /* free-table entries in LDS per heap (mult. of 64) */
+  int32_t lds_live;        /* live-table entries in LDS per heap (mult. of 64) */
+  int32_t groups;          /* persistent workgroups (0 = fill the device)      */
 } hda_tuning;
 
 typedef struct hda_batch_desc {
@@ -89,8 +96,9 @@ typedef struct hda_batch_desc {
   const int64_t *align;     /* device [H]: alignment bytes (power of two)       */
   const int32_t *algo;      /* device [H]: HDA_FIRST_FIT .. HDA_SEG_FIT         */
   const int64_t *req_off;   /* device [H+1]: CSR offsets into req/res           */
-  const int64_t *req;       /* device [req_off[H]]: encoded requests            */
-  int64_t *res;             /* device [req_off[H]]: results (written)           */
+  const int64_t *req;       /* device [req_off[H]]: encoded requests (non-null,
+                               also when req_off[H] == 0)                       */
+  int64_t *res;             /* device [req_off[H]]: results (written; non-null) */
   const int32_t *order;     /* device [H] or NULL: heap processing order
                                (a permutation; NULL = 0..H-1)                   */
   int64_t *state;           /* device or NULL: canonical states (written)       */

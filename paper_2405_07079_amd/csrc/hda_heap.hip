@@ -21,22 +21,31 @@ namespace {
 
 enum : int { kOpInit = 0, kOpAlloc = 1, kOpFree = 2, kOpDump = 3 };
 
-__global__ void heap_call(HeapHdr* hd, int op, int64_t arg, int64_t* out, int64_t cap) {
-  Tables t;
-  HeapRegs h;
-  load_heap(hd, t, h);
+template <int ALGO>
+__device__ void heap_call_t(HeapHdr* hd, int op, int64_t arg, int64_t* out, int64_t cap) {
+  const Cold c = heap_cold(hd);
+  WaveHeap<ALGO, 0, 0> w(c, load_regs(hd), hd->cf, hd->cl);
   int64_t r = 0;
   if (op == kOpInit) {
-    heap_init(t, h);
+    w.init();
   } else if (op == kOpAlloc) {
-    r = arg < 0 ? kEInval : op_alloc(t, h, arg);
+    r = arg < 0 ? kEInval : w.alloc_bytes(arg);
   } else if (op == kOpFree) {
-    r = op_free_offset(t, h, arg);
+    r = w.free_offset(arg);
   } else {
-    r = dump_state(t, h, out + 1, cap - 1);
+    r = w.dump(out + 1, cap - 1);
   }
-  store_heap(hd, h);
+  store_regs(hd, w.h);
   if (lane_id() == 0) out[0] = r;
+}
+
+__global__ void heap_call(HeapHdr* hd, int op, int64_t arg, int64_t* out, int64_t cap) {
+  switch (hd->algo) {
+    case kFirstFit: heap_call_t<kFirstFit>(hd, op, arg, out, cap); break;
+    case kNextFit: heap_call_t<kNextFit>(hd, op, arg, out, cap); break;
+    case kBestFit: heap_call_t<kBestFit>(hd, op, arg, out, cap); break;
+    default: heap_call_t<kSegFit>(hd, op, arg, out, cap); break;
+  }
 }
 
 std::atomic<int64_t> g_budget{0};  // 0 = unlimited

@@ -23,25 +23,28 @@ __host__ __device__ inline size_t heap_bytes(uint32_t cf, uint32_t cl) {
   return sizeof(HeapHdr) + (size_t)cf * 8 + (size_t)cf * 4 + (size_t)cl * 8;
 }
 
-__device__ inline void heap_tables(HeapHdr* hd, Tables& t) {
+__device__ inline Cold heap_cold(HeapHdr* hd) {
   uint8_t* base = reinterpret_cast<uint8_t*>(hd) + sizeof(HeapHdr);
-  t.lf = nullptr; t.lst = nullptr; t.ll = nullptr;  // no LDS part
-  t.kf = 0; t.kl = 0;
-  t.cf = hd->cf; t.cl = hd->cl;
-  t.gf = (HDA_GLOBAL Ent*)(base);
-  t.gst = (HDA_GLOBAL uint32_t*)(base + (size_t)t.cf * 8);
-  t.gl = (HDA_GLOBAL Ent*)(base + (size_t)t.cf * 12);
+  Cold c;
+  c.lf = nullptr; c.lst = nullptr; c.ll = nullptr;  // no LDS part
+  c.kf = 0; c.kl = 0;
+  c.cf = hd->cf; c.cl = hd->cl;
+  c.gf = (HDA_GLOBAL Ent*)(base);
+  c.gst = (HDA_GLOBAL uint32_t*)(base + (size_t)c.cf * 8);
+  c.gl = (HDA_GLOBAL Ent*)(base + (size_t)c.cf * 12);
+  return c;
 }
 
-__device__ inline void load_heap(HeapHdr* hd, Tables& t, HeapRegs& h) {
-  heap_tables(hd, t);
+__device__ inline HeapRegs load_regs(const HeapHdr* hd) {
+  HeapRegs h;
   h.F = hd->F; h.L = hd->L; h.ag = hd->ag; h.shift = hd->shift;
   h.rover = hd->rover; h.clock = hd->clock; h.algo = hd->algo; h.status = hd->status;
   h.arena = hd->arena;
   h.cnt = hd->cnt[lane_id()];
+  return h;
 }
 
-__device__ inline void store_heap(HeapHdr* hd, const HeapRegs& h) {
+__device__ inline void store_regs(HeapHdr* hd, const HeapRegs& h) {
   hd->cnt[lane_id()] = h.cnt;
   if (lane_id() == 0) {
     hd->F = h.F; hd->L = h.L; hd->rover = h.rover; hd->clock = h.clock;

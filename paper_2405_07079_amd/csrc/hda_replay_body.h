@@ -20,20 +20,24 @@ struct ReplayParams {
   const int64_t* state_off;
   int64_t* state_len;
   int32_t* status;
+  const int32_t* list;   // heaps this launch replays (one algorithm), or null
+  const uint32_t* count; // number of heaps in `list` (device), or null
   uint32_t* queue;       // heap counter (persistent mode)
-  Ent* spill_free;       // per wave slot: cf-kf entries
-  uint32_t* spill_stamp; // per wave slot: cf-kf stamps
-  Ent* spill_live;       // per wave slot: cl-kl entries
+  Ent* spill_free;       // per wave slot: cold free entries past LDS
+  uint32_t* spill_stamp; // per wave slot: their stamps
+  Ent* spill_live;       // per wave slot: cold live entries past LDS
   int64_t n_heaps;       // heaps handled by this launch
   int64_t first;         // index into `order` of the first heap
-  uint32_t kf, kl, cf, cl;
+  uint32_t cap_free, cap_live;   // total table capacities per heap
+  uint32_t kf, kl;               // cold entries kept in LDS per wave
+  uint32_t sf, sl;               // cold entries kept in device memory per wave
   uint32_t waves_per_group;
   uint32_t lds_wave_bytes;
   int use_queue;         // 1: pull heaps from the queue; 0: wave w takes heap w
 };
 
 // Validate heap parameters; on success fill the uniform heap registers.
-__device__ bool heap_params(const ReplayParams& p, int64_t heap, HeapRegs& h) {
+__device__ __forceinline__ bool heap_params(const ReplayParams& p, int64_t heap, HeapRegs& h) {
   const int64_t A = p.arena[heap], g = p.align[heap];
   const int algo = p.algo[heap];
   if (algo < 0 || algo > 3 || g <= 0 || (g & (g - 1)) || A <= 0 || (A % g) ||
@@ -44,52 +48,104 @@ __device__ bool heap_params(const ReplayParams& p, int64_t heap, HeapRegs& h) {
   h.shift = (uint32_t)__builtin_ctzll((uint64_t)g);
   h.ag = (uint32_t)(A >> h.shift);
   h.status = 0;
+  h.F = h.L = h.rover = h.clock = h.cnt = 0;
   return true;
 }
 
-__device__ void replay_one_heap(const ReplayParams& p, const Tables& t, int64_t heap) {
+template <int ALGO, int RF, int RL>
+__device__ void replay_heap(const ReplayParams& p, const Cold& c, const HeapRegs& regs,
+                            int64_t heap) {
   const uint32_t lane = lane_id();
+  const uint32_t hot_f = 64u * RF, hot_l = 64u * RL;
+  const uint32_t capF = p.cap_free, capL = p.cap_live;
+  WaveHeap<ALGO, RF, RL> w(c, regs, capF, capL);
+  (void)hot_f; (void)hot_l;
+  w.init();
   const int64_t b0 = p.req_off[heap], b1 = p.req_off[heap + 1];
-  HeapRegs h;
-  if (!heap_params(p, heap, h)) {
-    for (int64_t base = b0; base < b1; base += 64)
-      if (base + lane < b1) p.res[base + lane] = kEInval;
-    if (lane == 0) {
-      p.status[heap] = (int32_t)kEInval;
-      if (p.state_len) p.state_len[heap] = 0;
-    }
-    return;
-  }
-  heap_init(t, h);
-  // Requests are read 64 at a time (one per lane) and handed out in order
-  // with readlane; results collect in the lane of their slot and are written
-  // back 64 at a time.  The next chunk is prefetched while this one runs.
-  // Loads are clamped to the heap's last request instead of guarded by a
-  // lane-dependent branch, since the values feed wave-wide reads.
+  const uint64_t gm = (1ull << w.h.shift) - 1ull;
+  // Requests are read 64 at a time (one per lane) and decoded by all lanes at
+  // once: a free carries its draw, an allocation its size in granules (0 when
+  // larger than the arena) and, for segregated fit, its byte class.  Loads are
+  // clamped to the heap's last request instead of guarded by a lane-dependent
+  // branch, since the values feed wave-wide reads.
   const int64_t last = b1 - 1;
   int64_t nxt = b1 > b0 ? p.req[min<int64_t>(b0 + lane, last)] : 0;
   for (int64_t base = b0; base < b1; base += 64) {
-    const int64_t cur = nxt;
+    const int64_t q = nxt;
     nxt = p.req[min<int64_t>(base + 64 + lane, last)];
-    const uint32_t qlo = (uint32_t)cur, qhi = (uint32_t)((uint64_t)cur >> 32);
+    const bool is_free = q < 0;
+    const bool big = q > w.h.arena;
+    uint32_t sg = (uint32_t)(((uint64_t)q + gm) >> w.h.shift);
+    sg = sg == 0u ? 1u : sg;
+    const uint32_t w0 = is_free ? (uint32_t)~(uint64_t)q : (big ? 0u : sg);
+    const uint32_t w1 = ceil_log2_u32(sg) + w.h.shift;
+    const uint64_t mfree = ballot(is_free);
     const uint32_t n = (uint32_t)min<int64_t>(64, b1 - base);
-    int64_t out = 0;
+    uint32_t olo = 0, ohi = 0;
     for (uint32_t j = 0; j < n; ++j) {
-      const int64_t q = (int64_t)(((uint64_t)rdlane(qhi, j) << 32) | rdlane(qlo, j));
-      const int64_t r = op_request(t, h, q);
-      if (r == kENoMeta && h.status == 0) h.status = (int32_t)kENoMeta;
-      out = (lane == j) ? r : out;
+      const uint32_t v0 = rdlane(w0, j);
+      int64_t r;
+      if ((mfree >> j) & 1ull) {
+        r = w.free_draw(v0);
+      } else if (v0 == 0u) {
+        r = kFail;
+      } else {
+        r = w.alloc(v0, ALGO == kSegFit ? rdlane(w1, j) : 0u);
+      }
+      if (r == kENoMeta && w.h.status == 0) w.h.status = (int32_t)kENoMeta;
+      olo = put_lane(olo, j, (uint32_t)(uint64_t)r);
+      ohi = put_lane(ohi, j, (uint32_t)((uint64_t)r >> 32));
     }
-    if (base + lane < b1) p.res[base + lane] = out;
+    if (base + lane < b1) p.res[base + lane] = (int64_t)(((uint64_t)ohi << 32) | olo);
   }
-  int32_t st = h.status;
+  int32_t st = w.h.status;
   if (p.state) {
     const int64_t so = p.state_off[heap], cap = p.state_off[heap + 1] - so;
-    const int64_t need = dump_state(t, h, p.state + so, cap);
+    const int64_t need = w.dump(p.state + so, cap);
     if (lane == 0) p.state_len[heap] = need;
     if (need > cap && st == 0) st = (int32_t)kERange;
   }
   if (lane == 0) p.status[heap] = st;
+}
+
+// Heap with invalid parameters: every result and the status are E_INVAL.
+__device__ __forceinline__ void reject_heap(const ReplayParams& p, int64_t heap) {
+  const uint32_t lane = lane_id();
+  const int64_t b0 = p.req_off[heap], b1 = p.req_off[heap + 1];
+  for (int64_t base = b0; base < b1; base += 64)
+    if (base + lane < b1) p.res[base + lane] = kEInval;
+  if (lane == 0) {
+    p.status[heap] = (int32_t)kEInval;
+    if (p.state_len) p.state_len[heap] = 0;
+  }
+}
+
+// Replay one heap known to use algorithm ALGO (its parameters are checked
+// again; a heap that fails the check is rejected).
+template <int ALGO, int RF, int RL>
+__device__ __forceinline__ void replay_one_heap(const ReplayParams& p, const Cold& c, int64_t heap) {
+  HeapRegs h;
+  if (!heap_params(p, heap, h) || h.algo != ALGO) {
+    reject_heap(p, heap);
+    return;
+  }
+  replay_heap<ALGO, RF, RL>(p, c, h, heap);
+}
+
+// Any algorithm (used where one program must serve every heap).
+template <int RF, int RL>
+__device__ void replay_any_heap(const ReplayParams& p, const Cold& c, int64_t heap) {
+  HeapRegs h;
+  if (!heap_params(p, heap, h)) {
+    reject_heap(p, heap);
+    return;
+  }
+  switch (h.algo) {
+    case kFirstFit: replay_heap<kFirstFit, RF, RL>(p, c, h, heap); break;
+    case kNextFit: replay_heap<kNextFit, RF, RL>(p, c, h, heap); break;
+    case kBestFit: replay_heap<kBestFit, RF, RL>(p, c, h, heap); break;
+    default: replay_heap<kSegFit, RF, RL>(p, c, h, heap); break;
+  }
 }
 
 }  // namespace hda

@@ -24,6 +24,11 @@ __device__ __forceinline__ uint32_t rdlane(uint32_t v, uint32_t l) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
 }
 
+// Lane l of v receives the wave-uniform value x; other lanes keep v.
+__device__ __forceinline__ uint32_t put_lane(uint32_t v, uint32_t l, uint32_t x) {
+  return lane_id() == l ? x : v;
+}
+
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }

@@ -28,8 +28,20 @@ class HdaError(RuntimeError):
 
 
 class hda_tuning(ctypes.Structure):
-    _fields_ = [("heaps_per_group", ctypes.c_int32), ("lds_free", ctypes.c_int32),
+    _fields_ = [("heaps_per_group", ctypes.c_int32), ("reg_free", ctypes.c_int32),
+                ("reg_live", ctypes.c_int32), ("lds_free", ctypes.c_int32),
                 ("lds_live", ctypes.c_int32), ("groups", ctypes.c_int32)]
+
+
+TUNING_FIELDS = ("heaps_per_group", "reg_free", "reg_live", "lds_free", "lds_live", "groups")
+
+
+def tuning(**kw) -> tuple:
+    """A tuning tuple with the named fields set (others 0 = default)."""
+    bad = set(kw) - set(TUNING_FIELDS)
+    if bad:
+        raise ValueError(f"unknown tuning fields {bad}")
+    return tuple(int(kw.get(f, 0)) for f in TUNING_FIELDS)
 
 
 class hda_batch_desc(ctypes.Structure):
@@ -129,7 +141,7 @@ class DeviceBatch:
     meta_free: int
     meta_live: int
     workspace: "torch.Tensor | None" = None
-    tuning: tuple = (0, 0, 0, 0)
+    tuning: tuple = (0, 0, 0, 0, 0, 0)
 
     def desc(self) -> hda_batch_desc:
         d = hda_batch_desc()
@@ -155,14 +167,18 @@ def state_words(algo, blocks):
 
 
 def upload(batch, device="cuda", order="lpt", with_state=True, meta_free=4096,
-           meta_live=8192, tuning=(0, 0, 0, 0)) -> DeviceBatch:
+           meta_live=8192, tuning=(0, 0, 0, 0, 0, 0), share=None) -> DeviceBatch:
     """Copy a workloads.Batch to the device and allocate results, states,
-    status and the library's workspace (all torch-owned)."""
+    status and the library's workspace (all torch-owned).  With `share` (a
+    DeviceBatch of the same streams) its request, offset, arena, alignment
+    and order tensors are reused instead of copied again."""
     import torch
     H = batch.heaps
     t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dt)).to(device)  # noqa: E731
     lens = np.diff(batch.req_off)
-    if order == "lpt":      # longest trace first; ties keep heap order
+    if share is not None:
+        order_t = share.order
+    elif order == "lpt":      # longest trace first; ties keep heap order
         ordv = np.argsort(-lens, kind="stable").astype(np.int32)
         order_t = t(ordv, np.int32)
     elif order is None:
@@ -178,10 +194,15 @@ def upload(batch, device="cuda", order="lpt", with_state=True, meta_free=4096,
         state = torch.empty(int(so[-1]), dtype=torch.int64, device=device)
         state_off = t(so, np.int64)
         state_len = torch.zeros(H, dtype=torch.int64, device=device)
-    db = DeviceBatch(H, t(batch.arena, np.int64), t(batch.align, np.int64),
-                     t(batch.algo, np.int32), t(batch.req_off, np.int64),
-                     t(batch.req, np.int64),
-                     torch.empty(batch.requests, dtype=torch.int64, device=device),
+    # the library wants non-null request/result buffers even when empty
+    if share is not None:
+        arena_t, align_t, off_t, req_t = share.arena, share.align, share.req_off, share.req
+    else:
+        req = batch.req if batch.requests else np.zeros(1, np.int64)
+        arena_t, align_t = t(batch.arena, np.int64), t(batch.align, np.int64)
+        off_t, req_t = t(batch.req_off, np.int64), t(req, np.int64)
+    db = DeviceBatch(H, arena_t, align_t, t(batch.algo, np.int32), off_t, req_t,
+                     torch.empty(max(1, batch.requests), dtype=torch.int64, device=device),
                      order_t, state, state_off, state_len,
                      torch.zeros(H, dtype=torch.int32, device=device),
                      int(meta_free), int(meta_live), None, tuple(tuning))
@@ -197,11 +218,11 @@ def hda_replay_workspace(db: DeviceBatch) -> int:
     return int(n)
 
 
-def hda_replay_resolve(db: DeviceBatch) -> tuple:
+def hda_replay_resolve(db: DeviceBatch) -> dict:
     out = hda_tuning()
     _check(lib().hda_replay_resolve(ctypes.byref(db.desc()), ctypes.byref(out)),
            "hda_replay_resolve")
-    return (out.heaps_per_group, out.lds_free, out.lds_live, out.groups)
+    return {f: getattr(out, f) for f in TUNING_FIELDS}
 
 
 def hda_replay(db: DeviceBatch, stream=None) -> None:

@@ -28,13 +28,15 @@ def lib():
         vp = ctypes.c_void_p
         u32 = ctypes.c_uint32
         L.emu_replay.restype = ctypes.c_int
-        L.emu_replay.argtypes = [ctypes.c_int64] + [vp] * 10 + [u32] * 4 + [vp]
+        L.emu_replay.argtypes = [ctypes.c_int64] + [vp] * 10 + [ctypes.c_int] + [u32] * 4 + [vp]
         _lib = L
     return _lib
 
 
-def replay(batch, kf=64, kl=64, cf=4096, cl=4096):
-    """Replay a workloads.Batch heap by heap in the emulator."""
+def replay(batch, kf=64, kl=64, cf=4096, cl=4096, shape=2):
+    """Replay a workloads.Batch heap by heap in the emulator.  shape selects
+    the register part: 0 none, 1 = (1, 2) chunks, 2 = (4, 8) chunks; kf/kl are
+    the cold entries kept in "LDS"; cf/cl the table capacities."""
     H = batch.heaps
     P = lambda a: a.ctypes.data  # noqa: E731
     arena = np.ascontiguousarray(batch.arena, np.int64)
@@ -52,6 +54,6 @@ def replay(batch, kf=64, kl=64, cf=4096, cl=4096):
     status = np.zeros(H, np.int32)
     syncs = np.zeros(H, np.uint64)
     lib().emu_replay(H, P(arena), P(align), P(algo), P(off), P(req), P(res), P(state),
-                     P(so), P(sl), P(status), kf, kl, cf, cl, P(syncs))
+                     P(so), P(sl), P(status), int(shape), kf, kl, cf, cl, P(syncs))
     states = [state[so[h]:so[h] + sl[h]].copy() for h in range(H)]
     return res, states, status, syncs

@@ -22,14 +22,19 @@ namespace {
 
 struct LaneJob {
   const ReplayParams* p;
-  const Tables* t;
+  const Cold* c;
   int64_t heap;
+  int shape;
   int done;
 };
 LaneJob g_job;
 
 void lane_main() {
-  replay_one_heap(*g_job.p, *g_job.t, g_job.heap);
+  switch (g_job.shape) {
+    case 0: replay_any_heap<0, 0>(*g_job.p, *g_job.c, g_job.heap); break;
+    case 1: replay_any_heap<1, 2>(*g_job.p, *g_job.c, g_job.heap); break;
+    default: replay_any_heap<4, 8>(*g_job.p, *g_job.c, g_job.heap); break;
+  }
   // a finished lane keeps handing over until every lane has finished
   g_job.done++;
   for (;;) {
@@ -42,22 +47,32 @@ void lane_main() {
   }
 }
 
+const int kShapeRF[] = {0, 1, 4}, kShapeRL[] = {0, 2, 8};
+
 }  // namespace
 
+// shape: 0 = no register part, 1 = (1, 2) chunks, 2 = (4, 8) chunks in
+// registers.  kf/kl: cold entries in "LDS"; cap_free/cap_live: capacities.
 extern "C" int emu_replay(int64_t H, const int64_t* arena, const int64_t* align,
                           const int32_t* algo, const int64_t* req_off, const int64_t* req,
                           int64_t* res, int64_t* state, const int64_t* state_off,
-                          int64_t* state_len, int32_t* status, uint32_t kf, uint32_t kl,
-                          uint32_t cf, uint32_t cl, uint64_t* syncs) {
+                          int64_t* state_len, int32_t* status, int shape, uint32_t kf,
+                          uint32_t kl, uint32_t cap_free, uint32_t cap_live, uint64_t* syncs) {
   ReplayParams p;
   std::memset(&p, 0, sizeof(p));
   p.arena = arena; p.align = align; p.algo = algo; p.req_off = req_off; p.req = req;
   p.res = res; p.state = state; p.state_off = state_off; p.state_len = state_len;
   p.status = status;
-  p.kf = kf; p.kl = kl; p.cf = cf; p.cl = cl;
+  const uint32_t hf = 64u * kShapeRF[shape], hl = 64u * kShapeRL[shape];
+  const uint32_t coldF = cap_free > hf ? cap_free - hf : 0u;
+  const uint32_t coldL = cap_live > hl ? cap_live - hl : 0u;
+  kf = kf < coldF ? kf : coldF;
+  kl = kl < coldL ? kl : coldL;
+  p.cap_free = cap_free; p.cap_live = cap_live;
+  p.kf = kf; p.kl = kl; p.sf = coldF - kf; p.sl = coldL - kl;
   std::vector<uint8_t> lds(size_t(kf) * 12 + size_t(kl) * 8 + 16);
-  std::vector<Ent> gf(cf - kf + 64), gl(cl - kl + 64);
-  std::vector<uint32_t> gst(cf - kf + 64);
+  std::vector<Ent> gf(p.sf + 64), gl(p.sl + 64);
+  std::vector<uint32_t> gst(p.sf + 64);
   const size_t stack_bytes = 256 * 1024;
   std::vector<std::vector<uint8_t>> stacks(64, std::vector<uint8_t>(stack_bytes));
   EmuWave w;
@@ -67,13 +82,13 @@ extern "C" int emu_replay(int64_t H, const int64_t* arena, const int64_t* align,
     std::memset(lds.data(), 0xA5, lds.size());
     std::memset(gf.data(), 0xA5, gf.size() * sizeof(Ent));
     std::memset(gl.data(), 0xA5, gl.size() * sizeof(Ent));
-    Tables t;
-    t.lf = reinterpret_cast<Ent*>(lds.data());
-    t.lst = reinterpret_cast<uint32_t*>(lds.data() + size_t(kf) * 8);
-    t.ll = reinterpret_cast<Ent*>(lds.data() + size_t(kf) * 12);
-    t.gf = gf.data(); t.gst = gst.data(); t.gl = gl.data();
-    t.kf = kf; t.kl = kl; t.cf = cf; t.cl = cl;
-    g_job = LaneJob{&p, &t, h, 0};
+    Cold c;
+    c.lf = reinterpret_cast<Ent*>(lds.data());
+    c.lst = reinterpret_cast<uint32_t*>(lds.data() + size_t(kf) * 8);
+    c.ll = reinterpret_cast<Ent*>(lds.data() + size_t(kf) * 12);
+    c.gf = gf.data(); c.gst = gst.data(); c.gl = gl.data();
+    c.kf = kf; c.kl = kl; c.cf = coldF; c.cl = coldL;
+    g_job = LaneJob{&p, &c, h, shape, 0};
     w.syncs = 0;
     for (int l = 0; l < 64; ++l) {
       getcontext(&w.lane_ctx[l]);

@@ -61,6 +61,11 @@ inline uint32_t rdlane(uint32_t v, uint32_t l) {
   return exchange(v, [l](const uint64_t* x) { return (uint32_t)x[l & 63u]; });
 }
 
+// writelane: only the lane's own register changes, no exchange needed
+inline uint32_t put_lane(uint32_t v, uint32_t l, uint32_t x) {
+  return emu_lane == (l & 63u) ? x : v;
+}
+
 // the first active lane; in the core this is only used with all lanes active
 inline uint32_t uniform(uint32_t v) { return rdlane(v, 0); }
 

@@ -28,16 +28,19 @@ def check(batch, res, states, status, heaps=None):
 
 
 @pytest.mark.parametrize("algo", ALGOS)
-def test_single_heap_64KiB_default_tables(algo):
+def test_single_heap_64KiB_register_tables(algo):
     b = W.single_heap(n=4000).with_algo(algo)
-    res, states, status, _ = emu.replay(b, kf=256, kl=768, cf=4096, cl=8192)
+    res, states, status, _ = emu.replay(b, kf=64, kl=128, cf=4096, cl=8192, shape=2)
     check(b, res, states, status)
 
 
 @pytest.mark.parametrize("algo", ALGOS)
-def test_single_heap_spilling_tables(algo):
+@pytest.mark.parametrize("shape", (0, 1))
+def test_single_heap_spilling_tables(algo, shape):
+    """Small register part and LDS part: entries cross registers, LDS and
+    device memory."""
     b = W.single_heap(n=3000, seed=7).with_algo(algo)
-    res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=4096, cl=4096)
+    res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=4096, cl=4096, shape=shape)
     check(b, res, states, status)
 
 
@@ -51,20 +54,20 @@ def test_random_small_heaps():
                                    algo=int(rng.integers(0, 4)),
                                    max_granules=max(1, gran // int(rng.integers(1, 6)))))
     b = W.concat(parts)
-    res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=512, cl=512)
+    res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=512, cl=512, shape=1)
     check(b, res, states, status)
 
 
 @pytest.mark.parametrize("algo", ALGOS)
 def test_16MiB_heap(algo):
     b = W.uniform_batch(heaps=1, n=2500, algo=algo)
-    res, states, status, _ = emu.replay(b, kf=128, kl=128, cf=4096, cl=4096)
+    res, states, status, _ = emu.replay(b, kf=64, kl=128, cf=4096, cl=4096, shape=2)
     check(b, res, states, status)
 
 
 def test_capacity_exhausted_changes_nothing():
     b = W.uniform_batch(heaps=1, n=1500, algo=2)
-    res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=64, cl=64)
+    res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=64, cl=64, shape=1)
     ores, _, _ = oracle.replay_batch(b, want_state=False)
     assert status[0] == -4
     first = int(np.nonzero(res == -4)[0][0])

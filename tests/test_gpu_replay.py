@@ -18,14 +18,14 @@ def say(*a):
     print(*a, flush=True)
 
 
-def gpu_replay(batch, tuning=(0, 0, 0, 0), meta_free=4096, meta_live=8192,
+def gpu_replay(batch, tuning=(0, 0, 0, 0, 0, 0), meta_free=4096, meta_live=8192,
                per_heap=False, order="lpt", with_state=True):
     db = hda.upload(batch, order=order, tuning=tuning, meta_free=meta_free,
                     meta_live=meta_live, with_state=with_state)
     (hda.hda_replay_per_heap if per_heap else hda.hda_replay)(db)
     torch.cuda.synchronize()
     states = hda.states_to_host(db) if with_state else None
-    return db.res.cpu().numpy(), states, db.status.cpu().numpy()
+    return db.res.cpu().numpy()[:batch.requests], states, db.status.cpu().numpy()
 
 
 def check_against_oracle(batch, res, states, status, heaps=None):
@@ -86,19 +86,34 @@ def test_16MiB_heaps_reduced(algo):
     check_against_oracle(b, res, states, status)
 
 
+SPILL_TUNINGS = {
+    "lds64": hda.tuning(heaps_per_group=2, reg_free=-1, reg_live=-1, lds_free=64, lds_live=64),
+    "regs_then_device": hda.tuning(heaps_per_group=2, reg_free=2, reg_live=4, lds_free=-1,
+                                   lds_live=-1),
+    "regs_lds_device": hda.tuning(heaps_per_group=4, reg_free=2, reg_live=4, lds_free=64,
+                                  lds_live=64),
+}
+
+
 @pytest.mark.parametrize("algo", ALGOS)
-def test_spill_to_device_memory(algo):
-    """Only 64 free and 64 live entries in LDS: most of each table spills."""
+@pytest.mark.parametrize("where", sorted(SPILL_TUNINGS))
+def test_spill_to_device_memory(algo, where):
+    """Small register and LDS parts: most of each table spills to device
+    memory, and entries move between registers, LDS and device memory."""
     b = c2_like(24, 20_000, algo)
-    say(f"case: 24 x 16 MiB heaps, 20k requests, algo {algo}, lds 64/64")
-    res, states, status = gpu_replay(b, tuning=(2, 64, 64, 0))
+    say(f"case: 24 x 16 MiB heaps, 20k requests, algo {algo}, tables {where}")
+    res, states, status = gpu_replay(b, tuning=SPILL_TUNINGS[where])
     check_against_oracle(b, res, states, status)
 
 
 def test_tuning_does_not_change_results():
     b = W.concat([c2_like(16, 8000, a) for a in ALGOS], "mixed")
     ref = None
-    for tu in ((0, 0, 0, 0), (1, 64, 64, 0), (8, 128, 256, 0), (16, 64, 512, 3), (2, 512, 1024, 1)):
+    for tu in (hda.tuning(), hda.tuning(heaps_per_group=1, reg_free=-1, reg_live=-1),
+               hda.tuning(heaps_per_group=8, reg_free=2, reg_live=4, lds_free=128, lds_live=256),
+               hda.tuning(heaps_per_group=16, lds_free=64, lds_live=512, groups=3),
+               hda.tuning(heaps_per_group=2, reg_free=4, reg_live=8, lds_free=-1, lds_live=-1,
+                          groups=1)):
         say("case: tuning", tu)
         res, states, status = gpu_replay(b, tuning=tu)
         assert (status == 0).all()
@@ -172,7 +187,8 @@ def test_metadata_capacity_exhausted():
     requests that would need a new entry; earlier results are unaffected."""
     b = c2_like(2, 4000, 2)
     say("case: live-table capacity 64")
-    res, states, status = gpu_replay(b, tuning=(1, 64, 64, 0), meta_free=64, meta_live=64)
+    res, states, status = gpu_replay(b, tuning=hda.tuning(heaps_per_group=1), meta_free=64,
+                                     meta_live=64)
     ores, _, _ = oracle.replay_batch(b, want_state=False)
     assert (status == hda.HDA_E_NOMETA).all()
     for h in range(2):
