@@ -174,6 +174,109 @@ int hda_heap_state(const hda_heap *h, int64_t *buf, size_t cap, size_t *len);
  * 0 = unlimited (the default).  Returns the bytes currently held. */
 int64_t hda_set_meta_budget(int64_t bytes);
 
+/* ------------------------------------------------------------------------ */
+/* Serving: a device-resident allocator service with continuous batching.   */
+/* ------------------------------------------------------------------------ */
+
+/* A persistent kernel keeps every admitted heap's state in device memory
+ * and serves alloc/free requests that clients submit while it runs.  Heap
+ * slot s is served by wave s % waves, which applies that heap's requests in
+ * submission (FIFO) order; requests of different heaps run in parallel on
+ * different waves, and a request submitted while others are on the GPU is
+ * picked up by its wave as soon as the wave reaches it -- there is no batch
+ * boundary.  Requests travel through per-wave rings in pinned host memory
+ * (submission and completion); the kernel exits when hda_serve_stop raises
+ * its stop flag or after max_seconds, whichever comes first.  Each heap runs
+ * the same allocator code as hda_alloc / hda_free (Alg. 1-5). */
+typedef struct hda_server hda_server;
+
+typedef struct hda_serve_config {
+  int32_t waves;          /* service wavefronts; 0 = 2 per CU               */
+  int32_t max_heaps;      /* heap slots in the device pool (> 0)            */
+  int32_t slot_free;      /* free-table capacity per heap; 0 = 512          */
+  int32_t slot_live;      /* live-table capacity per heap; 0 = 512          */
+  int32_t ring_entries;   /* ring size per wave, power of two; 0 = 1024     */
+  int32_t reserved;
+  int64_t meta_budget;    /* bytes of heap metadata admitted at once;
+                             0 = every slot                                 */
+  double max_seconds;     /* watchdog on the kernel; 0 = 600                */
+} hda_serve_config;
+
+enum { HDA_OP_ALLOC = 1, HDA_OP_FREE = 2 };
+
+/* Start the service on the current device (allocates the pool and rings,
+ * launches the kernel on a library stream).  HDA_E_INVAL for bad config. */
+int hda_serve_start(const hda_serve_config *cfg, hda_server **out);
+
+/* Admit a heap (Alg. 6 init on its wave; asynchronous).  *heap receives its
+ * slot id.  HDA_E_NOMETA when the metadata budget or the slots are used up
+ * (close a heap and retry); HDA_E_INVAL for bad arena/align/algo as in
+ * hda_heap_create. */
+int hda_serve_open(hda_server *s, uint64_t arena_bytes, uint64_t align, int algo,
+                   int32_t *heap);
+
+/* Submit one request: op = HDA_OP_ALLOC with arg = size in bytes, or
+ * HDA_OP_FREE with arg = byte offset.  *ticket identifies the result.
+ * Blocks only while the heap's ring is full.  The result is the offset / -1
+ * / HDA_E_NOMETA for an allocation and HDA_OK / HDA_E_BADFREE for a free. */
+int hda_serve_submit(hda_server *s, int32_t heap, int op, int64_t arg, uint64_t *ticket);
+
+/* Non-blocking: *done = 1 and *result set once the ticket has completed.
+ * HDA_E_RANGE if the ticket is older than the ring keeps. */
+int hda_serve_poll(hda_server *s, uint64_t ticket, int64_t *result, int *done);
+
+/* Blocking form of hda_serve_poll; HDA_E_BUSY after 30 s without the
+ * completion (for instance once the service has stopped). */
+int hda_serve_wait(hda_server *s, uint64_t ticket, int64_t *result);
+
+/* Release a heap: waits for its queued requests, frees its slot and returns
+ * its metadata to the budget. */
+int hda_serve_close(hda_server *s, int32_t heap);
+
+/* Stop the kernel (drains nothing further), wait for it, free everything. */
+int hda_serve_stop(hda_server *s);
+
+/* Open-loop load: `clients` clients, each owning one heap, issue requests at
+ * Poisson arrival times of total rate `rate` per second (each arrival picks a
+ * client uniformly).  A client whose earliest-expiring live block has expired
+ * frees it, otherwise it allocates: with probability p_pow2 a size 2^k,
+ * k uniform in [pow2_lo, pow2_hi], else log-uniform in [size_lo, size_hi]
+ * bytes; a successful allocation lives ceil(Exp(lifetime_mean)) of that
+ * client's requests.  A client has at most one request in flight; arrivals
+ * meanwhile wait in its queue (their wait counts in their latency).
+ * Latency = completion seen by the host - arrival time. */
+typedef struct hda_load_config {
+  int32_t clients;
+  int32_t algo;
+  int32_t threads;        /* host threads driving clients; 0 = 4            */
+  int32_t log_clients;    /* first clients whose requests/results are logged */
+  int64_t log_cap;        /* entries per logged client                      */
+  int64_t *log;           /* host [log_clients * log_cap * 3]: row 0 is
+                             (0, arena, align), then (op, arg, result) per
+                             completed request in the client's order          */
+  int64_t *log_len;       /* host [log_clients]                             */
+  uint64_t arena_lo, arena_hi, align;   /* per-client arena: log-uniform   */
+  double rate;            /* arrivals per second                            */
+  double warmup_s, measure_s;
+  double p_pow2;
+  int32_t pow2_lo, pow2_hi;
+  uint64_t size_lo, size_hi;
+  double lifetime_mean;
+  uint64_t seed;
+  int32_t close_heaps;    /* 1: close every client heap at the end          */
+  int32_t reserved;
+} hda_load_config;
+
+typedef struct hda_load_report {
+  int64_t issued, completed, measured;  /* requests; measured = in window  */
+  int64_t alloc_ok, alloc_fail, frees, errors;
+  double window_s;                      /* measured window length           */
+  double throughput;                    /* completions per second in window */
+  double p50_us, p90_us, p99_us, p999_us, max_us, mean_us;
+} hda_load_report;
+
+int hda_serve_load(hda_server *s, const hda_load_config *cfg, hda_load_report *rep);
+
 /* Static description of an error code. */
 const char *hda_strerror(int code);
 

@@ -57,11 +57,48 @@ class hda_batch_desc(ctypes.Structure):
                 ("tuning", hda_tuning)]
 
 
+class hda_serve_config(ctypes.Structure):
+    _fields_ = [("waves", ctypes.c_int32), ("max_heaps", ctypes.c_int32),
+                ("slot_free", ctypes.c_int32), ("slot_live", ctypes.c_int32),
+                ("ring_entries", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("meta_budget", ctypes.c_int64), ("max_seconds", ctypes.c_double)]
+
+
+class hda_load_config(ctypes.Structure):
+    _fields_ = [("clients", ctypes.c_int32), ("algo", ctypes.c_int32),
+                ("threads", ctypes.c_int32), ("log_clients", ctypes.c_int32),
+                ("log_cap", ctypes.c_int64), ("log", ctypes.c_void_p),
+                ("log_len", ctypes.c_void_p),
+                ("arena_lo", ctypes.c_uint64), ("arena_hi", ctypes.c_uint64),
+                ("align", ctypes.c_uint64), ("rate", ctypes.c_double),
+                ("warmup_s", ctypes.c_double), ("measure_s", ctypes.c_double),
+                ("p_pow2", ctypes.c_double), ("pow2_lo", ctypes.c_int32),
+                ("pow2_hi", ctypes.c_int32), ("size_lo", ctypes.c_uint64),
+                ("size_hi", ctypes.c_uint64), ("lifetime_mean", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("close_heaps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class hda_load_report(ctypes.Structure):
+    _fields_ = [("issued", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("measured", ctypes.c_int64), ("alloc_ok", ctypes.c_int64),
+                ("alloc_fail", ctypes.c_int64), ("frees", ctypes.c_int64),
+                ("errors", ctypes.c_int64), ("window_s", ctypes.c_double),
+                ("throughput", ctypes.c_double), ("p50_us", ctypes.c_double),
+                ("p90_us", ctypes.c_double), ("p99_us", ctypes.c_double),
+                ("p999_us", ctypes.c_double), ("max_us", ctypes.c_double),
+                ("mean_us", ctypes.c_double)]
+
+
+HDA_OP_ALLOC, HDA_OP_FREE = 1, 2
+
 _lib = None
 
 EXPORTS = ["hda_replay_workspace", "hda_replay_resolve", "hda_replay",
            "hda_replay_per_heap", "hda_heap_create", "hda_heap_destroy", "hda_alloc",
-           "hda_free", "hda_heap_state", "hda_set_meta_budget", "hda_strerror"]
+           "hda_free", "hda_heap_state", "hda_set_meta_budget", "hda_strerror",
+           "hda_serve_start", "hda_serve_open", "hda_serve_submit", "hda_serve_poll",
+           "hda_serve_wait", "hda_serve_close", "hda_serve_stop", "hda_serve_load"]
 
 
 def lib():
@@ -97,6 +134,22 @@ def lib():
         L.hda_set_meta_budget.argtypes = [ctypes.c_int64]
         L.hda_strerror.restype = ctypes.c_char_p
         L.hda_strerror.argtypes = [ctypes.c_int]
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        for name, args in (
+                ("hda_serve_start", [ctypes.POINTER(hda_serve_config), ctypes.POINTER(vp)]),
+                ("hda_serve_open", [vp, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int, i32p]),
+                ("hda_serve_submit", [vp, ctypes.c_int32, ctypes.c_int, ctypes.c_int64, u64p]),
+                ("hda_serve_poll", [vp, ctypes.c_uint64, i64p, ctypes.POINTER(ctypes.c_int)]),
+                ("hda_serve_wait", [vp, ctypes.c_uint64, i64p]),
+                ("hda_serve_close", [vp, ctypes.c_int32]),
+                ("hda_serve_stop", [vp]),
+                ("hda_serve_load", [vp, ctypes.POINTER(hda_load_config),
+                                    ctypes.POINTER(hda_load_report)])):
+            fn = getattr(L, name)
+            fn.restype = ctypes.c_int
+            fn.argtypes = args
         _lib = L
     return _lib
 
@@ -291,3 +344,88 @@ class Heap:
         _check(lib().hda_heap_state(self._h, buf.ctypes.data, n.value, ctypes.byref(n)),
                "hda_heap_state")
         return buf
+
+
+# ---------------------------------------------------------------------------
+# Serving
+# ---------------------------------------------------------------------------
+
+class Server:
+    """The device-resident allocator service (a persistent kernel)."""
+
+    def __init__(self, max_heaps: int, waves: int = 0, slot_free: int = 0,
+                 slot_live: int = 0, ring_entries: int = 0, meta_budget: int = 0,
+                 max_seconds: float = 0.0):
+        cfg = hda_serve_config(int(waves), int(max_heaps), int(slot_free), int(slot_live),
+                               int(ring_entries), 0, int(meta_budget), float(max_seconds))
+        h = ctypes.c_void_p()
+        _check(lib().hda_serve_start(ctypes.byref(cfg), ctypes.byref(h)), "hda_serve_start")
+        self._s = h
+
+    def open(self, arena: int, align: int, algo: int) -> int:
+        heap = ctypes.c_int32()
+        _check(lib().hda_serve_open(self._s, int(arena), int(align), int(algo),
+                                    ctypes.byref(heap)), "hda_serve_open")
+        return heap.value
+
+    def submit(self, heap: int, op: int, arg: int) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().hda_serve_submit(self._s, int(heap), int(op), int(arg), ctypes.byref(t)),
+               "hda_serve_submit")
+        return t.value
+
+    def poll(self, ticket: int):
+        r, done = ctypes.c_int64(), ctypes.c_int()
+        _check(lib().hda_serve_poll(self._s, int(ticket), ctypes.byref(r), ctypes.byref(done)),
+               "hda_serve_poll")
+        return (r.value if done.value else None)
+
+    def wait(self, ticket: int) -> int:
+        r = ctypes.c_int64()
+        _check(lib().hda_serve_wait(self._s, int(ticket), ctypes.byref(r)), "hda_serve_wait")
+        return r.value
+
+    def alloc(self, heap: int, size: int) -> int:
+        return self.wait(self.submit(heap, HDA_OP_ALLOC, size))
+
+    def free(self, heap: int, offset: int) -> int:
+        return self.wait(self.submit(heap, HDA_OP_FREE, offset))
+
+    def close_heap(self, heap: int) -> None:
+        _check(lib().hda_serve_close(self._s, int(heap)), "hda_serve_close")
+
+    def load(self, clients: int, rate: float, warmup_s: float, measure_s: float,
+             algo: int = SEG_FIT, threads: int = 0, log_clients: int = 0, log_cap: int = 0,
+             arena=(64 << 20, 4 << 30), align: int = 512, p_pow2: float = 0.7,
+             pow2=(9, 28), size=(512, 256 << 20), lifetime_mean: float = 500.0,
+             seed: int = 4, close_heaps: bool = True):
+        """Run the open-loop client load; returns (report dict, logs or None).
+        logs[c] is an array of (op, arg, result) rows for client c."""
+        log = log_len = None
+        if log_clients:
+            log = np.zeros((log_clients, log_cap, 3), np.int64)
+            log_len = np.zeros(log_clients, np.int64)
+        cfg = hda_load_config(
+            int(clients), int(algo), int(threads), int(log_clients), int(log_cap),
+            None if log is None else log.ctypes.data,
+            None if log_len is None else log_len.ctypes.data,
+            int(arena[0]), int(arena[1]), int(align), float(rate), float(warmup_s),
+            float(measure_s), float(p_pow2), int(pow2[0]), int(pow2[1]), int(size[0]),
+            int(size[1]), float(lifetime_mean), int(seed), int(bool(close_heaps)), 0)
+        rep = hda_load_report()
+        _check(lib().hda_serve_load(self._s, ctypes.byref(cfg), ctypes.byref(rep)),
+               "hda_serve_load")
+        out = {f: getattr(rep, f) for f, _ in hda_load_report._fields_}
+        logs = None if log is None else [log[c, :log_len[c]] for c in range(log_clients)]
+        return out, logs
+
+    def stop(self) -> None:
+        if self._s:
+            _check(lib().hda_serve_stop(self._s), "hda_serve_stop")
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass
