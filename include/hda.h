@@ -80,7 +80,9 @@ enum {
  * 64*reg_live live entries are held in vector registers, the next lds_free /
  * lds_live entries in LDS, and the rest (up to the capacities) in device
  * memory.  0 = default for every field; -1 = none of that storage.  Register
- * shapes compiled in: (reg_free, reg_live) = (-1,-1), (4,8), (6,12), (8,16). */
+ * shapes compiled in: (reg_free, reg_live) = (-1,-1), (2,4), (4,-1), (6,-1),
+ * (4,8); the default is (4,-1) with up to 1024 live entries in LDS.  Any
+ * other pair is E_INVAL. */
 typedef struct hda_tuning {
   int32_t heaps_per_group; /* waves (= heaps in flight) per workgroup (1..16)  */
   int32_t reg_free;        /* free-table 64-entry chunks in registers          */

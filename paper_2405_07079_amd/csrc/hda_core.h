@@ -176,12 +176,28 @@ struct WaveHeap {
       : c(cold), h(regs), capF(cap_free), capL(cap_live) {}
 
   // ---- single entries (index wave-uniform) ----
+  // Register chunks are addressed with selects on the uniform chunk index,
+  // never with branches: a branch per chunk would make the compiler copy
+  // every table register at each join.
+  template <int R>
+  __device__ __forceinline__ static uint32_t pick(const uint32_t (&v)[R], uint32_t r) {
+    uint32_t x = opaque(v[0]);
+#pragma unroll
+    for (int k = 1; k < R; ++k) x = (r == (uint32_t)k) ? opaque(v[k]) : x;
+    return x;
+  }
+  template <int R>
+  __device__ __forceinline__ static void place(uint32_t (&v)[R], uint32_t r, uint32_t l,
+                                               uint32_t x) {
+    const bool me = lane_id() == l;
+#pragma unroll
+    for (int k = 0; k < R; ++k) v[k] = (me && r == (uint32_t)k) ? x : v[k];
+  }
+
   __device__ __forceinline__ void fread(uint32_t i, uint32_t& a, uint32_t& s) {
     if (i < HF) {
-      const uint32_t r = i >> 6, l = i & 63u;
-#pragma unroll
-      for (int k = 0; k < RF; ++k)
-        if (r == (uint32_t)k) { a = rdlane(fa[k], l); s = rdlane(fs[k], l); }
+      a = rdlane(pick(fa, i >> 6), i & 63u);
+      s = rdlane(pick(fs, i >> 6), i & 63u);
     } else {
       const Ent e = fget(c, i - HF);
       a = ent_a(e); s = ent_s(e);
@@ -189,42 +205,24 @@ struct WaveHeap {
   }
   __device__ __forceinline__ void fwrite(uint32_t i, uint32_t a, uint32_t s) {
     if (i < HF) {
-      const uint32_t r = i >> 6, l = i & 63u;
-#pragma unroll
-      for (int k = 0; k < RF; ++k)
-        if (r == (uint32_t)k) { fa[k] = put_lane(fa[k], l, a); fs[k] = put_lane(fs[k], l, s); }
+      place(fa, i >> 6, i & 63u, a);
+      place(fs, i >> 6, i & 63u, s);
     } else {
       fset(c, i - HF, mk_ent(a, s));
     }
   }
   __device__ __forceinline__ uint32_t stread(uint32_t i) {
-    uint32_t v = 0;
-    if (i < HF) {
-      const uint32_t r = i >> 6, l = i & 63u;
-#pragma unroll
-      for (int k = 0; k < RF; ++k)
-        if (r == (uint32_t)k) v = rdlane(fst[k], l);
-    } else {
-      v = sget(c, i - HF);
-    }
-    return v;
+    if (i < HF) return rdlane(pick(fst, i >> 6), i & 63u);
+    return sget(c, i - HF);
   }
   __device__ __forceinline__ void stwrite(uint32_t i, uint32_t v) {
-    if (i < HF) {
-      const uint32_t r = i >> 6, l = i & 63u;
-#pragma unroll
-      for (int k = 0; k < RF; ++k)
-        if (r == (uint32_t)k) fst[k] = put_lane(fst[k], l, v);
-    } else {
-      sset(c, i - HF, v);
-    }
+    if (i < HF) place(fst, i >> 6, i & 63u, v);
+    else sset(c, i - HF, v);
   }
   __device__ __forceinline__ void lread(uint32_t i, uint32_t& a, uint32_t& s) {
     if (i < HL) {
-      const uint32_t r = i >> 6, l = i & 63u;
-#pragma unroll
-      for (int k = 0; k < RL; ++k)
-        if (r == (uint32_t)k) { a = rdlane(la[k], l); s = rdlane(lz[k], l); }
+      a = rdlane(pick(la, i >> 6), i & 63u);
+      s = rdlane(pick(lz, i >> 6), i & 63u);
     } else {
       const Ent e = lget(c, i - HL);
       a = ent_a(e); s = ent_s(e);
@@ -232,10 +230,8 @@ struct WaveHeap {
   }
   __device__ __forceinline__ void lwrite(uint32_t i, uint32_t a, uint32_t s) {
     if (i < HL) {
-      const uint32_t r = i >> 6, l = i & 63u;
-#pragma unroll
-      for (int k = 0; k < RL; ++k)
-        if (r == (uint32_t)k) { la[k] = put_lane(la[k], l, a); lz[k] = put_lane(lz[k], l, s); }
+      place(la, i >> 6, i & 63u, a);
+      place(lz, i >> 6, i & 63u, s);
     } else {
       lset(c, i - HL, mk_ent(a, s));
     }
@@ -246,9 +242,7 @@ struct WaveHeap {
                                              uint32_t& st) {
     if (base < HF) {
       const uint32_t r = base >> 6;
-#pragma unroll
-      for (int k = 0; k < RF; ++k)
-        if (r == (uint32_t)k) { a = fa[k]; s = fs[k]; st = kSeg ? fst[k] : 0u; }
+      a = pick(fa, r); s = pick(fs, r); st = kSeg ? pick(fst, r) : 0u;
     } else {
       const Ent e = fchunk(c, base - HF);
       a = ent_a(e); s = ent_s(e);
@@ -258,22 +252,22 @@ struct WaveHeap {
   __device__ __forceinline__ void lchunk_any(uint32_t base, uint32_t& a, uint32_t& s) {
     if (base < HL) {
       const uint32_t r = base >> 6;
-#pragma unroll
-      for (int k = 0; k < RL; ++k)
-        if (r == (uint32_t)k) { a = la[k]; s = lz[k]; }
+      a = pick(la, r); s = pick(lz, r);
     } else {
       const Ent e = lchunk(c, base - HL);
       a = ent_a(e); s = ent_s(e);
     }
   }
 
-  // Visit every chunk of the free table: f(base, valid, a, s, stamp).
+  // Visit every chunk of the free table: f(base, valid, a, s, stamp).  The
+  // register chunks are all visited (entries past F are masked off), so the
+  // register part needs no branch.
   template <typename Fn>
   __device__ __forceinline__ void scan_free(Fn&& f) {
 #pragma unroll
     for (int k = 0; k < RF; ++k) {
       const uint32_t base = 64u * k;
-      if (base < h.F) f(base, base + lane_id() < h.F, fa[k], fs[k], kSeg ? fst[k] : 0u);
+      f(base, base + lane_id() < h.F, fa[k], fs[k], kSeg ? fst[k] : 0u);
     }
     for (uint32_t base = HF; base < h.F; base += 64u) {
       const Ent e = fchunk(c, base - HF);

@@ -141,7 +141,8 @@ struct Shape {
             (const void*)replay_kernel<kNextFit, RF, RL>,                          \
             (const void*)replay_kernel<kBestFit, RF, RL>,                          \
             (const void*)replay_kernel<kSegFit, RF, RL>}}
-const Shape kShapes[] = {HDA_SHAPE(0, 0), HDA_SHAPE(2, 4), HDA_SHAPE(4, 8)};
+const Shape kShapes[] = {HDA_SHAPE(0, 0), HDA_SHAPE(2, 4), HDA_SHAPE(4, 0), HDA_SHAPE(6, 0),
+                         HDA_SHAPE(4, 8)};
 #undef HDA_SHAPE
 constexpr int kDefaultShape = 2;
 
@@ -218,7 +219,10 @@ bool make_plan(const hda_batch_desc* d, bool persistent, Plan* pl) {
   const uint32_t coldL = capL > 64u * shape->rl ? capL - 64u * shape->rl : 0u;
   // LDS part of the cold tables: 0 = default, -1 = none
   const uint32_t want_kf = tu.lds_free > 0 ? (uint32_t)tu.lds_free : (tu.lds_free < 0 ? 0u : 64u);
-  const uint32_t want_kl = tu.lds_live > 0 ? (uint32_t)tu.lds_live : (tu.lds_live < 0 ? 0u : 128u);
+  // default LDS share of the live table: all of it up to 1024 entries when
+  // the shape keeps none in registers
+  const uint32_t dflt_kl = shape->rl == 0 ? 1024u : 128u;
+  const uint32_t want_kl = tu.lds_live > 0 ? (uint32_t)tu.lds_live : (tu.lds_live < 0 ? 0u : dflt_kl);
   const uint32_t kf = std::min(want_kf, coldF), kl = std::min(want_kl, coldL);
   const uint32_t lds_wave = kf * 12u + kl * 8u;
   const uint32_t lds_group = lds_wave * W;

@@ -29,6 +29,15 @@ __device__ __forceinline__ uint32_t put_lane(uint32_t v, uint32_t l, uint32_t x)
   return lane_id() == l ? x : v;
 }
 
+// A value the optimiser may not trace back to the memory it was loaded
+// from.  Selecting between table registers through it keeps a select chain
+// from being folded into one load at a computed offset, which would pin the
+// whole table in private (scratch) memory.
+__device__ __forceinline__ uint32_t opaque(uint32_t v) {
+  asm("" : "+v"(v));
+  return v;
+}
+
 __device__ __forceinline__ uint32_t uniform(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }

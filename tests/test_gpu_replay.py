@@ -92,6 +92,8 @@ SPILL_TUNINGS = {
                                    lds_live=-1),
     "regs_lds_device": hda.tuning(heaps_per_group=4, reg_free=2, reg_live=4, lds_free=64,
                                   lds_live=64),
+    "free_regs_live_lds": hda.tuning(heaps_per_group=4, reg_free=6, reg_live=-1, lds_free=64,
+                                     lds_live=128),
 }
 
 
@@ -113,7 +115,8 @@ def test_tuning_does_not_change_results():
                hda.tuning(heaps_per_group=8, reg_free=2, reg_live=4, lds_free=128, lds_live=256),
                hda.tuning(heaps_per_group=16, lds_free=64, lds_live=512, groups=3),
                hda.tuning(heaps_per_group=2, reg_free=4, reg_live=8, lds_free=-1, lds_live=-1,
-                          groups=1)):
+                          groups=1),
+               hda.tuning(heaps_per_group=4, reg_free=6, reg_live=-1, lds_live=2048)):
         say("case: tuning", tu)
         res, states, status = gpu_replay(b, tuning=tu)
         assert (status == 0).all()
