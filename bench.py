@@ -31,6 +31,40 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 BYTES_PER_REQUEST = 16         # 8 B request read + 8 B result written
 
 
+def kernel_source_hash():
+    """sha256 over the kernel sources: counter figures recorded for other
+    sources no longer describe the kernel being timed."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2405_07079_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(algo_names):
+    """HBM bytes per launch from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, calibrated on a copy kernel), averaged over the timed
+    launches; None when the summary is missing or was taken on other kernel
+    sources."""
+    path = os.path.join(ROOT, "profiles", "replay_c2_hbm_traffic.txt")
+    try:
+        with open(path) as f:
+            line = [x for x in f if x.startswith("machine-readable: ")][-1]
+        rec = json.loads(line.split(": ", 1)[1])
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    t = rec.get("traffic_bytes_per_launch", {})
+    if not all(a in t for a in algo_names):
+        return None
+    return float(np.mean([t[a] for a in algo_names]))
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -51,7 +85,7 @@ def main():
     ap.add_argument("--requests", type=int, default=100_000)
     ap.add_argument("--per-heap-sample", type=int, default=64,
                     help="heaps per algorithm replayed one launch per heap")
-    ap.add_argument("--cpu-sample", type=int, default=128,
+    ap.add_argument("--cpu-sample", type=int, default=1024,
                     help="heaps per algorithm replayed by the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tuning", type=str, default="0,0,0,0,0,0",
@@ -199,7 +233,9 @@ def main():
                                       "one launch per heap",
                             "batched_speedup": value / per_heap_value},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": recorded_traffic([W.ALGO_NAMES[a] for a in algos]),
+                     "traffic_unit": "bytes per launch",
                      "kernel": "replay_kernel",
                      "avg_launch_ms": avg_launch_s * 1e3,
                      "bytes_per_request": BYTES_PER_REQUEST,
