@@ -76,13 +76,17 @@ enum {
  *   segregated fit only: for each class k = 0..63 (sizes in [2^k, 2^(k+1))):
  *     len_k, then the block addresses from list head to tail.
  */
-/* Where each heap's tables live.  The first 64*reg_free free entries and
- * 64*reg_live live entries are held in vector registers, the next lds_free /
- * lds_live entries in LDS, and the rest (up to the capacities) in device
- * memory.  0 = default for every field; -1 = none of that storage.  Register
- * shapes compiled in: (reg_free, reg_live) = (-1,-1), (2,4), (4,-1), (6,-1),
- * (4,8); the default is (4,-1) with up to 1024 live entries in LDS.  Any
- * other pair is E_INVAL. */
+/* Where each heap's tables live.  Default (lean) path: the first
+ * 64*reg_free free-table entries are held in vector registers (reg_free = 4
+ * or 6; 0 = 4), the next lds_free free entries and lds_live live entries in
+ * LDS (defaults 128 and 1024).  A heap whose tables outgrow these tiers
+ * before reaching meta_free / meta_live is replayed again from its first
+ * request on the general path, inside the same call; results do not depend
+ * on the tuning.  reg_free = -1 selects the general path for every heap: no
+ * registers, lds_free / lds_live entries in LDS (defaults 64 and 1024), the
+ * rest in device memory (workspace).  reg_live must be 0 or -1 (the live
+ * table is never held in registers).  0 = default for every field; -1 = none
+ * of that storage.  Any other value is E_INVAL. */
 typedef struct hda_tuning {
   int32_t heaps_per_group; /* waves (= heaps in flight) per workgroup (1..16)  */
   int32_t reg_free;        /* free-table 64-entry chunks in registers          */

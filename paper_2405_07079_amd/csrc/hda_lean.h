@@ -1,0 +1,430 @@
+// Lean replay core: one wavefront replays one heap with exactly two storage
+// tiers.  Free-table entry i lives in lane i % 64 of 64-entry chunk i / 64;
+// the first RF chunks are VGPRs and the rest, up to kf entries, LDS.  The
+// live table is in LDS.  Selection (Sec. II, Sec. IV, Sec. V-A) and the
+// neighbour search of coalescing (Alg. 2, Alg. 5) are wave-wide scans over the
+// chunks followed by one DPP reduction.
+//
+// Unused free slots hold address ~0 and size 0.  Such a slot never fits a
+// request (every request is at least one granule) and never borders a block
+// (no block starts or ends at granule ~0), so every scan covers whole chunks
+// with no bounds mask.
+//
+// When a table would outgrow these tiers before it reaches the capacity the
+// caller asked for, the heap stops with kOverflow and is replayed from its
+// first request by the general core (hda_core.h), whose tables spill to
+// device memory.  Results are the same on both paths.
+//
+// Same rules as the general core: values that feed a cross-lane operation are
+// never produced under a lane-dependent branch, and every LDS access is
+// preceded by wave_sync().
+#pragma once
+#include <stdint.h>
+
+#include "hda_core.h"
+
+namespace hda {
+
+constexpr int64_t kOverflow = -100;      // internal: the fast tiers are too small
+// Segregated-fit key of a free block: byte class in the top 6 bits, push
+// stamp below, so the head of class c (the block pushed last) is the largest
+// key under (c + 1) << 26.
+constexpr uint32_t kKeyShift = 26;
+constexpr uint32_t kStampLimit = 1u << kKeyShift;
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) { return ~wave_min(~v); }
+
+template <int R>
+__device__ __forceinline__ uint32_t reg_pick(const uint32_t (&v)[R], uint32_t r) {
+  uint32_t x = opaque(v[0]);
+#pragma unroll
+  for (int k = 1; k < R; ++k) x = (r == (uint32_t)k) ? opaque(v[k]) : x;
+  return x;
+}
+// Lane l of chunk r becomes x; nothing changes when r >= R.
+template <int R>
+__device__ __forceinline__ void reg_place(uint32_t (&v)[R], uint32_t r, uint32_t l, uint32_t x) {
+  const bool me = lane_id() == l;
+#pragma unroll
+  for (int k = 0; k < R; ++k) v[k] = (me && r == (uint32_t)k) ? x : v[k];
+}
+
+struct LeanLds {
+  HDA_LDS Ent* cf;        // free entries 64*RF .. 64*RF + kf - 1
+  HDA_LDS uint32_t* ck;   // their segregated-fit keys
+  HDA_LDS Ent* lv;        // live entries 0 .. kl - 1
+  uint32_t kf, kl;
+};
+
+template <int ALGO, int RF>
+struct LeanHeap {
+  static constexpr bool kSeg = ALGO == kSegFit;
+  static constexpr uint32_t HF = 64u * RF;
+  static_assert(RF >= 1, "at least one register chunk");
+
+  LeanLds m;
+  uint32_t fa[RF], fs[RF], fk[RF];
+  uint32_t cnt;                   // segregated fit: lane k = free blocks of byte class k
+  int64_t arena;
+  uint32_t shift, ag;
+  uint32_t F, L, rover, clock;
+  uint32_t limF, limL;            // F and L never exceed these
+  bool metaF, metaL;              // the limit is the caller's capacity (E_NOMETA), not the tiers
+
+  __device__ __forceinline__ LeanHeap(const LeanLds& lds, const HeapRegs& h, uint32_t capF,
+                                      uint32_t capL)
+      : m(lds), arena(h.arena), shift(h.shift), ag(h.ag) {
+    const uint32_t fastF = HF + lds.kf, fastL = lds.kl;
+    limF = capF < fastF ? capF : fastF;
+    limL = capL < fastL ? capL : fastL;
+    metaF = capF <= fastF;
+    metaL = capL <= fastL;
+  }
+
+  __device__ __forceinline__ uint32_t byte_class(uint32_t sg) const {
+    return floor_log2_u32(sg) + shift;
+  }
+  __device__ __forceinline__ uint32_t seg_key(uint32_t sg) { return (byte_class(sg) << kKeyShift) | clock++; }
+  __device__ __forceinline__ void cnt_add(uint32_t cls, int d) {
+    cnt += (lane_id() == cls) ? (uint32_t)d : 0u;
+  }
+
+  // ---- free-table entries by wave-uniform index ----
+  __device__ __forceinline__ uint32_t size_at(uint32_t j) {
+    if (j < HF) return rdlane(reg_pick(fs, j >> 6), j & 63u);
+    wave_sync();
+    return uniform(ent_s(m.cf[j - HF]));
+  }
+  __device__ __forceinline__ void read(uint32_t j, uint32_t& a, uint32_t& s, uint32_t& k) {
+    if (j < HF) {
+      const uint32_t r = j >> 6, l = j & 63u;
+      a = rdlane(reg_pick(fa, r), l);
+      s = rdlane(reg_pick(fs, r), l);
+      k = kSeg ? rdlane(reg_pick(fk, r), l) : 0u;
+    } else {
+      wave_sync();
+      const Ent e = m.cf[j - HF];
+      a = uniform(ent_a(e));
+      s = uniform(ent_s(e));
+      k = kSeg ? uniform(m.ck[j - HF]) : 0u;
+    }
+  }
+  // The register chunks take a select each (none matches a cold index), so
+  // the tables are never merged across a branch.  An LDS entry is stored by
+  // every lane with the same value: a store guarded by a lane test would be
+  // merged by the optimiser with the uniform test around it into one
+  // divergent branch, which turns the heap's counters into per-lane values.
+  __device__ __forceinline__ void write(uint32_t j, uint32_t a, uint32_t s, uint32_t k) {
+    const uint32_t r = j >> 6, l = j & 63u;
+    reg_place(fa, r, l, a);
+    reg_place(fs, r, l, s);
+    if (kSeg) reg_place(fk, r, l, k);
+    if (j >= HF) {
+      wave_sync();
+      m.cf[j - HF] = mk_ent(a, s);
+      if (kSeg) m.ck[j - HF] = k;
+    }
+  }
+  __device__ __forceinline__ void clear(uint32_t j) { write(j, kNone, 0u, 0u); }
+
+  // ---- live table ----
+  __device__ __forceinline__ void live_read(uint32_t i, uint32_t& a, uint32_t& s) {
+    wave_sync();
+    const Ent e = m.lv[i];
+    a = uniform(ent_a(e));
+    s = uniform(ent_s(e));
+  }
+  __device__ __forceinline__ void live_write(uint32_t i, uint32_t a, uint32_t s) {
+    wave_sync();
+    m.lv[i] = mk_ent(a, s);  // every lane, same value (see write())
+  }
+
+  // Visit every chunk holding entries: f(chunk, a, s, key).
+  template <typename Fn>
+  __device__ __forceinline__ void scan(Fn&& f) {
+#pragma unroll
+    for (int k = 0; k < RF; ++k) f((uint32_t)k, fa[k], fs[k], kSeg ? fk[k] : 0u);
+    for (uint32_t c = RF; 64u * c < F; ++c) {
+      const uint32_t i = 64u * (c - RF) + lane_id();
+      wave_sync();
+      const Ent e = m.cf[i];
+      const uint32_t k = kSeg ? m.ck[i] : 0u;
+      f(c, ent_a(e), ent_s(e), k);
+    }
+  }
+
+  // Alg. 6: one free block [0, A).
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int k = 0; k < RF; ++k) { fa[k] = kNone; fs[k] = 0u; fk[k] = 0u; }
+    wave_sync();
+    for (uint32_t i = lane_id(); i < m.kf; i += 64u) {
+      m.cf[i] = mk_ent(kNone, 0u);
+      if (kSeg) m.ck[i] = 0u;
+    }
+    F = 1; L = 0; rover = 0; clock = 1; cnt = 0;
+    write(0, 0u, ag, kSeg ? seg_key(ag) : 0u);
+    if (kSeg) cnt_add(byte_class(ag), 1);
+  }
+
+  // Remove free entry j: the last entry moves into its place and the last
+  // slot is cleared.
+  __device__ __forceinline__ void remove(uint32_t j) {
+    const uint32_t last = F - 1u;
+    if (j != last) {
+      uint32_t a, s, k;
+      read(last, a, s, k);
+      write(j, a, s, k);
+    }
+    clear(last);
+    F = last;
+  }
+
+  // Selection.  On success j is the chosen entry and (a, s) its block.
+  __device__ __forceinline__ bool select(uint32_t sg, uint32_t kreq, uint32_t& j, uint32_t& a,
+                                         uint32_t& s) {
+    if constexpr (ALGO == kFirstFit || ALGO == kNextFit) {
+      // first fit: lowest address among blocks that fit.  Next fit: blocks
+      // are taken in cyclic order starting at the first whose end is past the
+      // rover; since free blocks do not overlap, that order is the order of
+      // end - rover - 1 taken mod 2^32.  The block ending exactly at the rover
+      // (last in that order) has key ~0, which the scan cannot tell from
+      // "none", so it is looked for separately when nothing else fits.
+      const uint32_t nr = ~rover;
+      uint32_t best = kNone, bc = 0;
+      scan([&](uint32_t c, uint32_t ea, uint32_t es, uint32_t) {
+        const uint32_t t = es >= sg ? (ALGO == kFirstFit ? ea : ea + es + nr) : kNone;
+        const bool lt = t < best;
+        best = lt ? t : best;
+        bc = lt ? c : bc;
+      });
+      const uint32_t K = wave_min(best);
+      uint64_t mk;
+      uint32_t end;  // next fit: end of the chosen block
+      if (K != kNone) {
+        mk = ballot(best == K);
+        end = K - nr;
+      } else {
+        if (ALGO == kFirstFit) return false;
+        uint64_t any = 0ull;
+        scan([&](uint32_t c, uint32_t ea, uint32_t es, uint32_t) {
+          const bool hit = es >= sg && ea + es == rover;
+          any |= ballot(hit);
+          bc = hit ? c : bc;
+        });
+        if (any == 0ull) return false;
+        mk = any;
+        end = rover;
+      }
+      const uint32_t l = ctz64(mk);
+      j = 64u * rdlane(bc, l) + l;
+      s = size_at(j);
+      a = ALGO == kFirstFit ? K : end - s;
+      return true;
+    } else if constexpr (ALGO == kBestFit) {
+      // smallest size, then lowest address
+      uint32_t bs = kNone, ba = kNone, bc = 0;
+      scan([&](uint32_t c, uint32_t ea, uint32_t es, uint32_t) {
+        const uint32_t t = es >= sg ? es : kNone;
+        const bool take = t < bs || (t == bs && ea < ba);
+        bs = take ? t : bs;
+        ba = take ? ea : ba;
+        bc = take ? c : bc;
+      });
+      const uint32_t K = wave_min(bs);
+      if (K == kNone) return false;
+      uint64_t mk = ballot(bs == K);
+      if (__builtin_popcountll(mk) > 1) {
+        const uint32_t A2 = wave_min(bs == K ? ba : kNone);
+        mk = ballot(bs == K && ba == A2);
+      }
+      const uint32_t l = ctz64(mk);
+      j = 64u * rdlane(bc, l) + l;
+      a = rdlane(ba, l);
+      s = K;
+      return true;
+    } else {
+      // segregated fit: the first non-empty class at or above the request's,
+      // and in it the block pushed last (Alg. 4)
+      if (kreq >= 64u) return false;
+      const uint64_t bm = ballot(cnt != 0u) & (~0ull << kreq);
+      if (bm == 0ull) return false;
+      const uint32_t c = ctz64(bm);
+      const uint32_t lim = c >= 63u ? kNone : (c + 1u) << kKeyShift;
+      uint32_t best = 0u, bc = 0;
+      scan([&](uint32_t ch, uint32_t, uint32_t, uint32_t ek) {
+        const bool take = ek < lim && ek > best;
+        best = take ? ek : best;
+        bc = take ? ch : bc;
+      });
+      const uint32_t K = wave_max(best);
+      const uint32_t l = ctz64(ballot(best == K));
+      j = 64u * rdlane(bc, l) + l;
+      uint32_t k;
+      read(j, a, s, k);
+      return true;
+    }
+  }
+
+  // Allocate sg granules; kreq is the request's byte class (segregated fit).
+  // Returns the byte offset, -1, kENoMeta or kOverflow.
+  __device__ __forceinline__ int64_t alloc(uint32_t sg, uint32_t kreq) {
+    uint32_t j, a, s;
+    if (!select(sg, kreq, j, a, s)) return kFail;
+    if (L >= limL) return metaL ? kENoMeta : kOverflow;
+    if (s > sg) {  // Alg. 1 / Alg. 4: the block is cut from the low end
+      if (kSeg && clock >= kStampLimit) return kOverflow;
+      write(j, a + sg, s - sg, kSeg ? seg_key(s - sg) : 0u);
+      if (kSeg) { cnt_add(byte_class(s), -1); cnt_add(byte_class(s - sg), 1); }
+    } else {
+      remove(j);
+      if (kSeg) cnt_add(byte_class(s), -1);
+    }
+    live_write(L, a, sg);
+    ++L;
+    if (ALGO == kNextFit) rover = a + sg;
+    return (int64_t)((uint64_t)a << shift);
+  }
+
+  // Free live entry idx: coalesce with free neighbours (Alg. 2 / Alg. 5),
+  // then drop the entry from the live table (the last one moves into its
+  // place).  Returns the byte offset, kENoMeta or kOverflow.
+  __device__ __forceinline__ int64_t free_index(uint32_t idx) {
+    if (kSeg && clock >= kStampLimit) return kOverflow;
+    uint32_t x, sz;
+    live_read(idx, x, sz);
+    const uint32_t xe = x + sz;
+    uint64_t ML = 0ull, MR = 0ull;
+    uint32_t cl = 0, cr = 0;
+    scan([&](uint32_t c, uint32_t ea, uint32_t es, uint32_t) {
+      const bool il = ea + es == x, ir = ea == xe;
+      ML |= ballot(il);
+      MR |= ballot(ir);
+      cl = il ? c : cl;
+      cr = ir ? c : cr;
+    });
+    if ((ML | MR) == 0ull) {
+      if (F >= limF) return metaF ? kENoMeta : kOverflow;
+      write(F, x, sz, kSeg ? seg_key(sz) : 0u);
+      if (kSeg) cnt_add(byte_class(sz), 1);
+      ++F;
+    } else if (MR == 0ull) {
+      const uint32_t l = ctz64(ML), jl = 64u * rdlane(cl, l) + l;
+      const uint32_t sl = size_at(jl);
+      write(jl, x - sl, sl + sz, kSeg ? seg_key(sl + sz) : 0u);
+      if (kSeg) { cnt_add(byte_class(sl), -1); cnt_add(byte_class(sl + sz), 1); }
+    } else if (ML == 0ull) {
+      const uint32_t l = ctz64(MR), jr = 64u * rdlane(cr, l) + l;
+      const uint32_t sr = size_at(jr);
+      write(jr, x, sz + sr, kSeg ? seg_key(sz + sr) : 0u);
+      if (kSeg) { cnt_add(byte_class(sr), -1); cnt_add(byte_class(sz + sr), 1); }
+    } else {
+      const uint32_t ll = ctz64(ML), jl = 64u * rdlane(cl, ll) + ll;
+      const uint32_t lr = ctz64(MR), jr = 64u * rdlane(cr, lr) + lr;
+      const uint32_t sl = size_at(jl), sr = size_at(jr), ms = sl + sz + sr;
+      const uint32_t last = F - 1u;
+      uint32_t keep;  // slot that ends up holding the merged block
+      if (jr == last) {
+        keep = jl;
+      } else if (jl == last) {
+        keep = jr;
+      } else {
+        keep = jl;
+        uint32_t a, s, k;
+        read(last, a, s, k);
+        write(jr, a, s, k);
+      }
+      write(keep, x - sl, ms, kSeg ? seg_key(ms) : 0u);
+      clear(last);
+      if (kSeg) {
+        cnt_add(byte_class(sl), -1);
+        cnt_add(byte_class(sr), -1);
+        cnt_add(byte_class(ms), 1);
+      }
+      F = last;
+    }
+    const uint32_t last = L - 1u;
+    if (idx != last) {
+      uint32_t a, s;
+      live_read(last, a, s);
+      live_write(idx, a, s);
+    }
+    L = last;
+    return (int64_t)((uint64_t)x << shift);
+  }
+
+  // Replay free: r is the 32-bit draw, the victim is live[(r * L) >> 32];
+  // nothing live -> -1.
+  __device__ __forceinline__ int64_t free_draw(uint32_t r) {
+    if (L == 0u) return kFail;
+    return free_index((uint32_t)(((uint64_t)r * (uint64_t)L) >> 32));
+  }
+
+  // Canonical state, same format as the general core (hda.h).
+  __device__ int64_t dump(int64_t* out, int64_t cap) {
+    const uint32_t lane = lane_id();
+    const int64_t need = 4 + 2 * (int64_t)F + 2 * (int64_t)L + (kSeg ? 64 + (int64_t)F : 0);
+    if (out == nullptr || need > cap) return need;
+    const uint32_t sh = shift;
+    if (lane == 0) out[0] = F;
+    int64_t* fo = out + 1;
+    // free blocks ranked by address
+    scan([&](uint32_t c, uint32_t a, uint32_t s, uint32_t) {
+      const bool v = 64u * c + lane < F;
+      uint32_t rank = 0;
+      for (uint32_t j = 0; j < F; ++j) {
+        uint32_t aj, sj, kj;
+        read(j, aj, sj, kj);
+        rank += aj < a ? 1u : 0u;
+      }
+      if (v) {
+        fo[2 * rank] = (int64_t)((uint64_t)a << sh);
+        fo[2 * rank + 1] = (int64_t)((uint64_t)s << sh);
+      }
+    });
+    int64_t* lo = out + 1 + 2 * (int64_t)F;
+    if (lane == 0) lo[0] = L;
+    for (uint32_t base = 0; base < L; base += 64u) {
+      const uint32_t i = base + lane;
+      wave_sync();
+      const Ent e = m.lv[i < L ? i : 0u];
+      if (i < L) {
+        lo[1 + 2 * i] = (int64_t)((uint64_t)ent_a(e) << sh);
+        lo[2 + 2 * i] = (int64_t)((uint64_t)ent_s(e) << sh);
+      }
+    }
+    int64_t* tail = lo + 1 + 2 * (int64_t)L;
+    const uint64_t bm = ballot(cnt != 0u);
+    if (lane == 0) {
+      tail[0] = ALGO == kNextFit ? (int64_t)((uint64_t)rover << sh) : -1;
+      tail[1] = kSeg ? (int64_t)bm : 0;
+    }
+    if constexpr (kSeg) {
+      int64_t* ls = tail + 2;
+      const uint32_t region = 64u + F;  // words of the class-list section
+      // header position of class `lane`: sum over lower classes of (1 + count)
+      uint32_t hdr = 0, acc = 0;
+      for (uint32_t k = 0; k < 64u; ++k) {
+        hdr = (lane == k) ? acc : hdr;
+        acc += 1u + rdlane(cnt, k);
+      }
+      if (hdr < region) ls[hdr] = cnt;
+      // within a class, blocks from the last pushed (largest key) down
+      scan([&](uint32_t c, uint32_t a, uint32_t, uint32_t key) {
+        const bool v = 64u * c + lane < F;
+        const uint32_t cls = v ? key >> kKeyShift : 0u;
+        uint32_t rank = 0;
+        for (uint32_t j = 0; j < F; ++j) {
+          uint32_t aj, sj, kj;
+          read(j, aj, sj, kj);
+          rank += ((kj >> kKeyShift) == cls && kj > key) ? 1u : 0u;
+        }
+        const uint32_t hc = shfl(hdr, cls);
+        if (v && hc + 1u + rank < region) ls[hc + 1u + rank] = (int64_t)((uint64_t)a << sh);
+      });
+    }
+    return need;
+  }
+};
+
+}  // namespace hda

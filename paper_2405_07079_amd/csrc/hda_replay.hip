@@ -27,6 +27,10 @@ using namespace hda;
 namespace {
 
 constexpr int kClasses = 5;  // four algorithms + invalid
+// Queue words in the workspace: one per algorithm, then the overflow pass's
+// queue and the overflow count.
+constexpr int kQueueWords = 6;
+constexpr int kOvfQueue = 4, kOvfCount = 5;
 
 struct ClassifyParams {
   const int64_t* arena;
@@ -79,8 +83,8 @@ __global__ void __launch_bounds__(1024) classify_kernel(ClassifyParams q) {
       for (int a = 0; a < kClasses; ++a) v = (lane == (uint32_t)a) ? cnt[a] : v;
       counts[lane] = v;
       q.counts[lane] = v;
-      if (lane < 4u) q.queues[lane] = 0u;
     }
+    if (lane < (uint32_t)kQueueWords) q.queues[lane] = 0u;
   }
   __syncthreads();
   const uint32_t bad = counts[4];
@@ -96,24 +100,13 @@ __global__ void __launch_bounds__(1024) classify_kernel(ClassifyParams q) {
   }
 }
 
-template <int ALGO, int RF, int RL>
-__global__ void __launch_bounds__(1024) replay_kernel(ReplayParams p) {
-  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  const uint32_t wave = threadIdx.x >> 6;
-  HDA_LDS uint8_t* mine = (HDA_LDS uint8_t*)smem + (size_t)wave * p.lds_wave_bytes;
-  const uint64_t slot = (uint64_t)blockIdx.x * p.waves_per_group + wave;
-  Cold c;
-  c.lf = (HDA_LDS Ent*)(mine);
-  c.lst = (HDA_LDS uint32_t*)(mine + (size_t)p.kf * 8);
-  c.ll = (HDA_LDS Ent*)(mine + (size_t)p.kf * 12);
-  c.gf = (HDA_GLOBAL Ent*)(p.spill_free + slot * p.sf);
-  c.gst = (HDA_GLOBAL uint32_t*)(p.spill_stamp + slot * p.sf);
-  c.gl = (HDA_GLOBAL Ent*)(p.spill_live + slot * p.sl);
-  c.kf = p.kf; c.kl = p.kl;
-  c.cf = p.kf + p.sf; c.cl = p.kl + p.sl;
+// Persistent loop: waves pull heap positions from p.queue until the list is
+// used up; with use_queue = 0 wave `slot` takes list entry first + slot.
+template <typename Fn>
+__device__ __forceinline__ void for_each_heap(const ReplayParams& p, uint64_t slot, Fn&& f) {
   const int64_t n = p.use_queue ? (int64_t)*p.count : p.n_heaps;
   if (!p.use_queue) {
-    if ((int64_t)slot < n) replay_one_heap<ALGO, RF, RL>(p, c, p.list[p.first + (int64_t)slot]);
+    if ((int64_t)slot < n) f((int64_t)p.list[p.first + (int64_t)slot]);
     return;
   }
   // A wave can take at most every heap, so the loop is bounded even if the
@@ -126,29 +119,81 @@ __global__ void __launch_bounds__(1024) replay_kernel(ReplayParams p) {
     uint32_t hq = atomicAdd(p.queue, lane_id() == 0 ? 1u : 0u);
     hq = rdlane(hq, 0);
     if ((int64_t)hq >= n) break;
-    replay_one_heap<ALGO, RF, RL>(p, c, p.list[hq]);
+    f((int64_t)p.list[hq]);
   }
 }
 
-// Register-resident table shapes the library is compiled for:
-// (free chunks, live chunks) of 64 entries each, one kernel per algorithm.
-struct Shape {
-  int rf, rl;
+// General path: tables in LDS, then device memory (per wave slot).
+__device__ __forceinline__ Cold general_tiers(const ReplayParams& p, HDA_LDS uint8_t* mine,
+                                              uint64_t slot) {
+  Cold c;
+  c.lf = (HDA_LDS Ent*)(mine);
+  c.lst = (HDA_LDS uint32_t*)(mine + (size_t)p.kf * 8);
+  c.ll = (HDA_LDS Ent*)(mine + (size_t)p.kf * 12);
+  c.gf = (HDA_GLOBAL Ent*)(p.spill_free + slot * p.sf);
+  c.gst = (HDA_GLOBAL uint32_t*)(p.spill_stamp + slot * p.sf);
+  c.gl = (HDA_GLOBAL Ent*)(p.spill_live + slot * p.sl);
+  c.kf = p.kf; c.kl = p.kl;
+  c.cf = p.kf + p.sf; c.cl = p.kl + p.sl;
+  return c;
+}
+
+// General-path kernel for one algorithm.
+template <int ALGO>
+__global__ void __launch_bounds__(1024) general_kernel(ReplayParams p) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  const uint32_t wave = uniform(threadIdx.x >> 6);  // the same in every lane of the wave
+  HDA_LDS uint8_t* mine = (HDA_LDS uint8_t*)smem + (size_t)wave * p.lds_wave_bytes;
+  const uint64_t slot = (uint64_t)blockIdx.x * p.waves_per_group + wave;
+  const Cold c = general_tiers(p, mine, slot);
+  for_each_heap(p, slot, [&](int64_t heap) __attribute__((always_inline)) { replay_one_heap<ALGO, 0, 0>(p, c, heap); });
+}
+
+// Second pass of the lean path: heaps of any algorithm that outgrew the lean
+// tiers, replayed from the start on the general path.
+__global__ void __launch_bounds__(1024) overflow_kernel(ReplayParams p) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  const uint32_t wave = uniform(threadIdx.x >> 6);  // the same in every lane of the wave
+  HDA_LDS uint8_t* mine = (HDA_LDS uint8_t*)smem + (size_t)wave * p.lds_wave_bytes;
+  const uint64_t slot = (uint64_t)blockIdx.x * p.waves_per_group + wave;
+  const Cold c = general_tiers(p, mine, slot);
+  for_each_heap(p, slot, [&](int64_t heap) __attribute__((always_inline)) { replay_any_heap<0, 0>(p, c, heap); });
+}
+
+// Lean-path kernel for one algorithm with RF free-table chunks in VGPRs.
+template <int ALGO, int RF>
+__global__ void __launch_bounds__(1024) lean_kernel(ReplayParams p) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  const uint32_t wave = uniform(threadIdx.x >> 6);  // the same in every lane of the wave
+  HDA_LDS uint8_t* mine = (HDA_LDS uint8_t*)smem + (size_t)wave * p.lds_wave_bytes;
+  const uint64_t slot = (uint64_t)blockIdx.x * p.waves_per_group + wave;
+  LeanLds lds;
+  lds.cf = (HDA_LDS Ent*)(mine);
+  lds.ck = (HDA_LDS uint32_t*)(mine + (size_t)p.kf * 8);
+  lds.lv = (HDA_LDS Ent*)(mine + (size_t)p.kf * 12);
+  lds.kf = p.kf;
+  lds.kl = p.kl;
+  for_each_heap(p, slot, [&](int64_t heap) __attribute__((always_inline)) { lean_one_heap<ALGO, RF>(p, lds, heap); });
+}
+
+// Kernel sets: rf = free-table chunks in VGPRs (0 = general path).
+struct KernelSet {
+  int rf;
   const void* fn[4];
 };
-#define HDA_SHAPE(RF, RL)                                                          \
-  {RF, RL, {(const void*)replay_kernel<kFirstFit, RF, RL>,                         \
-            (const void*)replay_kernel<kNextFit, RF, RL>,                          \
-            (const void*)replay_kernel<kBestFit, RF, RL>,                          \
-            (const void*)replay_kernel<kSegFit, RF, RL>}}
-const Shape kShapes[] = {HDA_SHAPE(0, 0), HDA_SHAPE(2, 4), HDA_SHAPE(4, 0), HDA_SHAPE(6, 0),
-                         HDA_SHAPE(4, 8)};
-#undef HDA_SHAPE
-constexpr int kDefaultShape = 2;
+#define HDA_LEAN(RF)                                                                    \
+  {RF, {(const void*)lean_kernel<kFirstFit, RF>, (const void*)lean_kernel<kNextFit, RF>, \
+        (const void*)lean_kernel<kBestFit, RF>, (const void*)lean_kernel<kSegFit, RF>}}
+const KernelSet kSets[] = {
+    {0, {(const void*)general_kernel<kFirstFit>, (const void*)general_kernel<kNextFit>,
+         (const void*)general_kernel<kBestFit>, (const void*)general_kernel<kSegFit>}},
+    HDA_LEAN(4), HDA_LEAN(6)};
+#undef HDA_LEAN
+constexpr int kDefaultRF = 4;
 
-const Shape* find_shape(int rf, int rl) {
-  for (const Shape& s : kShapes)
-    if (s.rf == rf && s.rl == rl) return &s;
+const KernelSet* find_set(int rf) {
+  for (const KernelSet& s : kSets)
+    if (s.rf == rf) return &s;
   return nullptr;
 }
 
@@ -188,12 +233,33 @@ DeviceCtx* device_ctx() {
 
 uint32_t round64(int64_t x) { return (uint32_t)((x + 63) / 64 * 64); }
 
-struct Plan {
-  const Shape* shape;
-  uint32_t W, capF, capL, kf, kl, sf, sl, lds_wave, lds_group;
-  int64_t groups[4], slots[4];
-  size_t off_counts, off_queues, off_lists, off_free[4], off_stamp[4], off_live[4], bytes;
+// Launch geometry and tiers of one pass (the main per-algorithm launches, or
+// the overflow pass of the lean path).
+struct Pass {
+  uint32_t W = 1, kf = 0, kl = 0, sf = 0, sl = 0, lds_wave = 0, lds_group = 0;
+  int64_t groups[4] = {1, 1, 1, 1}, slots[4] = {1, 1, 1, 1};
+  size_t off_free[4] = {}, off_stamp[4] = {}, off_live[4] = {};
 };
+
+struct Plan {
+  const KernelSet* set;
+  bool lean;
+  uint32_t capF, capL;
+  Pass main, ovf;
+  size_t off_counts, off_queues, off_lists, off_ovf, bytes;
+};
+
+int occupancy_groups(const void* fn, uint32_t W, uint32_t lds_group, int cus, int32_t want,
+                     int64_t n_heaps) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, (int)(64 * W), (size_t)lds_group) !=
+          hipSuccess ||
+      nb < 1)
+    nb = 1;
+  int64_t groups = want > 0 ? want : (int64_t)nb * cus;
+  const int64_t need = (n_heaps + W - 1) / W;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(groups, need));
+}
 
 // Fill defaults and derive the launches and the workspace layout.
 bool make_plan(const hda_batch_desc* d, bool persistent, Plan* pl) {
@@ -202,62 +268,70 @@ bool make_plan(const hda_batch_desc* d, bool persistent, Plan* pl) {
   const hda_tuning& tu = d->tuning;
   const DeviceCtx* dc = device_ctx();
   if (!dc) return false;
-  // register shape: 0 = default, -1 = none
-  const Shape* shape = &kShapes[kDefaultShape];
-  if (tu.reg_free != 0 || tu.reg_live != 0) {
-    shape = find_shape(tu.reg_free < 0 ? 0 : tu.reg_free, tu.reg_live < 0 ? 0 : tu.reg_live);
-    if (!shape) return false;
-  }
+  // free chunks in registers: 0 = default, -1 = none (general path); the
+  // live table is never held in registers
+  const int rf = tu.reg_free == 0 ? kDefaultRF : (tu.reg_free < 0 ? 0 : tu.reg_free);
+  const KernelSet* set = find_set(rf);
+  if (!set || tu.reg_live > 0) return false;
   if (tu.heaps_per_group < 0 || tu.heaps_per_group > 16 || (tu.lds_free > 0 && tu.lds_free % 64) ||
       (tu.lds_live > 0 && tu.lds_live % 64) || tu.groups < 0)
     return false;
+  const bool lean = rf > 0;
   uint32_t W = tu.heaps_per_group > 0 ? (uint32_t)tu.heaps_per_group : 4u;
   if (!persistent) W = 1;
   const uint32_t capF = round64(d->meta_free > 0 ? d->meta_free : 4096);
   const uint32_t capL = round64(d->meta_live > 0 ? d->meta_live : 8192);
-  const uint32_t coldF = capF > 64u * shape->rf ? capF - 64u * shape->rf : 0u;
-  const uint32_t coldL = capL > 64u * shape->rl ? capL - 64u * shape->rl : 0u;
-  // LDS part of the cold tables: 0 = default, -1 = none
-  const uint32_t want_kf = tu.lds_free > 0 ? (uint32_t)tu.lds_free : (tu.lds_free < 0 ? 0u : 64u);
-  // default LDS share of the live table: all of it up to 1024 entries when
-  // the shape keeps none in registers
-  const uint32_t dflt_kl = shape->rl == 0 ? 1024u : 128u;
-  const uint32_t want_kl = tu.lds_live > 0 ? (uint32_t)tu.lds_live : (tu.lds_live < 0 ? 0u : dflt_kl);
-  const uint32_t kf = std::min(want_kf, coldF), kl = std::min(want_kl, coldL);
-  const uint32_t lds_wave = kf * 12u + kl * 8u;
-  const uint32_t lds_group = lds_wave * W;
-  if (lds_group > dc->max_lds) return false;
-  pl->shape = shape;
-  pl->W = W; pl->capF = capF; pl->capL = capL;
-  pl->kf = kf; pl->kl = kl; pl->sf = coldF - kf; pl->sl = coldL - kl;
-  pl->lds_wave = lds_wave; pl->lds_group = lds_group;
+  const uint32_t hotF = 64u * (uint32_t)rf;
+  const uint32_t coldF = capF > hotF ? capF - hotF : 0u;
+  // LDS entries: 0 = default, -1 = none
+  const uint32_t want_kf = tu.lds_free > 0 ? (uint32_t)tu.lds_free
+                                           : (tu.lds_free < 0 ? 0u : (lean ? 128u : 64u));
+  const uint32_t want_kl = tu.lds_live > 0 ? (uint32_t)tu.lds_live : (tu.lds_live < 0 ? 0u : 1024u);
+  Pass& m = pl->main;
+  m.W = W;
+  m.kf = std::min(want_kf, coldF);
+  m.kl = std::min(want_kl, capL);
+  m.sf = lean ? 0u : coldF - m.kf;
+  m.sl = lean ? 0u : capL - m.kl;
+  m.lds_wave = m.kf * 12u + m.kl * 8u;
+  m.lds_group = m.lds_wave * W;
+  if (m.lds_group > dc->max_lds) return false;
   for (int a = 0; a < 4; ++a) {
-    int64_t groups = 1;
-    if (persistent) {
-      // resident workgroups per CU as the runtime computes it (LDS,
-      // registers, wave slots)
-      int nb = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, shape->fn[a], (int)(64 * W),
-                                                       (size_t)lds_group) != hipSuccess || nb < 1)
-        nb = 1;
-      groups = tu.groups > 0 ? tu.groups : (int64_t)nb * dc->cus;
-      const int64_t need = (d->n_heaps + W - 1) / W;
-      groups = std::max<int64_t>(1, std::min<int64_t>(groups, need));
-    }
-    pl->groups[a] = groups;
-    pl->slots[a] = groups * W;
+    m.groups[a] = persistent ? occupancy_groups(set->fn[a], W, m.lds_group, dc->cus, tu.groups,
+                                                d->n_heaps)
+                             : 1;
+    m.slots[a] = m.groups[a] * W;
   }
+  Pass& o = pl->ovf;
+  if (lean) {
+    o.W = 1;
+    o.kf = std::min(64u, capF);
+    o.kl = std::min(512u, capL);
+    o.sf = capF - o.kf;
+    o.sl = capL - o.kl;
+    o.lds_wave = o.kf * 12u + o.kl * 8u;
+    o.lds_group = o.lds_wave;
+    const int64_t g = std::max<int64_t>(1, std::min<int64_t>(2 * (int64_t)dc->cus, d->n_heaps));
+    for (int a = 0; a < 4; ++a) { o.groups[a] = a == 0 ? g : 0; o.slots[a] = a == 0 ? g : 0; }
+  }
+  pl->set = set;
+  pl->lean = lean;
+  pl->capF = capF;
+  pl->capL = capL;
   auto align_up = [](size_t x) { return (x + 255) / 256 * 256; };
-  size_t o = 0;
-  pl->off_counts = o; o = align_up(o + kClasses * 4);
-  pl->off_queues = o; o = align_up(o + 4 * 4);
-  pl->off_lists = o; o = align_up(o + (size_t)kClasses * std::max<int64_t>(d->n_heaps, 1) * 4);
-  for (int a = 0; a < 4; ++a) {
-    pl->off_free[a] = o; o = align_up(o + (size_t)pl->slots[a] * pl->sf * 8);
-    pl->off_stamp[a] = o; o = align_up(o + (size_t)pl->slots[a] * pl->sf * 4);
-    pl->off_live[a] = o; o = align_up(o + (size_t)pl->slots[a] * pl->sl * 8);
-  }
-  pl->bytes = o;
+  size_t off = 0;
+  pl->off_counts = off; off = align_up(off + kClasses * 4);
+  pl->off_queues = off; off = align_up(off + kQueueWords * 4);
+  const size_t H1 = (size_t)std::max<int64_t>(d->n_heaps, 1);
+  pl->off_lists = off; off = align_up(off + (size_t)kClasses * H1 * 4);
+  pl->off_ovf = off; off = align_up(off + H1 * 4);
+  for (Pass* ps : {&pl->main, &pl->ovf})
+    for (int a = 0; a < 4; ++a) {
+      ps->off_free[a] = off; off = align_up(off + (size_t)ps->slots[a] * ps->sf * 8);
+      ps->off_stamp[a] = off; off = align_up(off + (size_t)ps->slots[a] * ps->sf * 4);
+      ps->off_live[a] = off; off = align_up(off + (size_t)ps->slots[a] * ps->sl * 8);
+    }
+  pl->bytes = off;
   return true;
 }
 
@@ -282,7 +356,9 @@ ClassifyParams classify_params(const hda_batch_desc* d, const Plan& pl) {
   return q;
 }
 
-ReplayParams replay_params(const hda_batch_desc* d, const Plan& pl, int a) {
+// Parameters of one launch: pass `ps`, algorithm a (or the overflow pass).
+ReplayParams replay_params(const hda_batch_desc* d, const Plan& pl, const Pass& ps, int a,
+                           bool overflow) {
   ReplayParams p;
   std::memset(&p, 0, sizeof(p));
   p.arena = d->arena; p.align = d->align; p.algo = d->algo;
@@ -290,29 +366,42 @@ ReplayParams replay_params(const hda_batch_desc* d, const Plan& pl, int a) {
   p.state = d->state; p.state_off = d->state_off; p.state_len = d->state_len;
   p.status = d->status;
   uint8_t* ws = static_cast<uint8_t*>(d->workspace);
-  p.list = reinterpret_cast<const int32_t*>(ws + pl.off_lists) + (int64_t)a * d->n_heaps;
-  p.count = reinterpret_cast<const uint32_t*>(ws + pl.off_counts) + a;
-  p.queue = reinterpret_cast<uint32_t*>(ws + pl.off_queues) + a;
-  p.spill_free = reinterpret_cast<Ent*>(ws + pl.off_free[a]);
-  p.spill_stamp = reinterpret_cast<uint32_t*>(ws + pl.off_stamp[a]);
-  p.spill_live = reinterpret_cast<Ent*>(ws + pl.off_live[a]);
+  uint32_t* queues = reinterpret_cast<uint32_t*>(ws + pl.off_queues);
+  int32_t* ovf = reinterpret_cast<int32_t*>(ws + pl.off_ovf);
+  if (overflow) {
+    p.list = ovf;
+    p.count = queues + kOvfCount;
+    p.queue = queues + kOvfQueue;
+  } else {
+    p.list = reinterpret_cast<const int32_t*>(ws + pl.off_lists) + (int64_t)a * d->n_heaps;
+    p.count = reinterpret_cast<const uint32_t*>(ws + pl.off_counts) + a;
+    p.queue = queues + a;
+  }
+  p.ovf_list = ovf;
+  p.ovf_count = queues + kOvfCount;
+  p.spill_free = reinterpret_cast<Ent*>(ws + ps.off_free[a]);
+  p.spill_stamp = reinterpret_cast<uint32_t*>(ws + ps.off_stamp[a]);
+  p.spill_live = reinterpret_cast<Ent*>(ws + ps.off_live[a]);
   p.n_heaps = d->n_heaps;
   p.first = 0;
   p.cap_free = pl.capF; p.cap_live = pl.capL;
-  p.kf = pl.kf; p.kl = pl.kl; p.sf = pl.sf; p.sl = pl.sl;
-  p.waves_per_group = pl.W;
-  p.lds_wave_bytes = pl.lds_wave;
+  p.kf = ps.kf; p.kl = ps.kl; p.sf = ps.sf; p.sl = ps.sl;
+  p.waves_per_group = ps.W;
+  p.lds_wave_bytes = ps.lds_wave;
   p.use_queue = 1;
   return p;
 }
 
-bool set_lds_attr(const Shape* s, uint32_t bytes) {
+bool set_lds_attr(const void* fn, uint32_t bytes) {
   if (bytes <= 65536) return true;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
+         hipSuccess;
+}
+
+bool set_lds_attrs(const Plan& pl) {
   for (int a = 0; a < 4; ++a)
-    if (hipFuncSetAttribute(s->fn[a], hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) !=
-        hipSuccess)
-      return false;
-  return true;
+    if (!set_lds_attr(pl.set->fn[a], pl.main.lds_group)) return false;
+  return !pl.lean || set_lds_attr((const void*)overflow_kernel, pl.ovf.lds_group);
 }
 
 hipError_t launch(const void* fn, dim3 grid, dim3 block, uint32_t lds, hipStream_t st,
@@ -325,6 +414,16 @@ int classify(const hda_batch_desc* d, const Plan& pl, hipStream_t s) {
   ClassifyParams q = classify_params(d, pl);
   hipLaunchKernelGGL(classify_kernel, dim3(1), dim3(1024), 0, s, q);
   return hipGetLastError() == hipSuccess ? HDA_OK : HDA_E_DEVICE;
+}
+
+// The lean path's second pass, on stream s after the main launches.
+int launch_overflow(const hda_batch_desc* d, const Plan& pl, hipStream_t s) {
+  if (!pl.lean) return HDA_OK;
+  ReplayParams p = replay_params(d, pl, pl.ovf, 0, true);
+  return launch((const void*)overflow_kernel, dim3((uint32_t)pl.ovf.groups[0]), dim3(64),
+                pl.ovf.lds_group, s, p) == hipSuccess
+             ? HDA_OK
+             : HDA_E_DEVICE;
 }
 
 }  // namespace
@@ -340,12 +439,12 @@ size_t hda_replay_workspace(const hda_batch_desc* d) {
 int hda_replay_resolve(const hda_batch_desc* d, hda_tuning* out) {
   Plan pl;
   if (!out || !make_plan(d, true, &pl)) return HDA_E_INVAL;
-  out->heaps_per_group = (int32_t)pl.W;
-  out->reg_free = pl.shape->rf > 0 ? pl.shape->rf : -1;
-  out->reg_live = pl.shape->rl > 0 ? pl.shape->rl : -1;
-  out->lds_free = pl.kf > 0 ? (int32_t)pl.kf : -1;
-  out->lds_live = pl.kl > 0 ? (int32_t)pl.kl : -1;
-  out->groups = (int32_t)pl.groups[0];
+  out->heaps_per_group = (int32_t)pl.main.W;
+  out->reg_free = pl.set->rf > 0 ? pl.set->rf : -1;
+  out->reg_live = -1;
+  out->lds_free = pl.main.kf > 0 ? (int32_t)pl.main.kf : -1;
+  out->lds_live = pl.main.kl > 0 ? (int32_t)pl.main.kl : -1;
+  out->groups = (int32_t)pl.main.groups[0];
   return HDA_OK;
 }
 
@@ -356,20 +455,22 @@ int hda_replay(const hda_batch_desc* d, void* stream) {
   if (!d->workspace || d->workspace_bytes < pl.bytes) return HDA_E_RANGE;
   DeviceCtx* dc = device_ctx();
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (!dc || !set_lds_attr(pl.shape, pl.lds_group)) return HDA_E_DEVICE;
+  if (!dc || !set_lds_attrs(pl)) return HDA_E_DEVICE;
   std::lock_guard<std::mutex> g(dc->enqueue);
   int rc = classify(d, pl, s);
   if (rc != HDA_OK) return rc;
   if (hipEventRecord(dc->fork, s) != hipSuccess) return HDA_E_DEVICE;
   for (int a = 0; a < 4; ++a) {
-    ReplayParams p = replay_params(d, pl, a);
+    ReplayParams p = replay_params(d, pl, pl.main, a, false);
     if (hipStreamWaitEvent(dc->side[a], dc->fork, 0) != hipSuccess ||
-        launch(pl.shape->fn[a], dim3((uint32_t)pl.groups[a]), dim3(64 * pl.W), pl.lds_group,
-               dc->side[a], p) != hipSuccess ||
+        launch(pl.set->fn[a], dim3((uint32_t)pl.main.groups[a]), dim3(64 * pl.main.W),
+               pl.main.lds_group, dc->side[a], p) != hipSuccess ||
         hipEventRecord(dc->join[a], dc->side[a]) != hipSuccess ||
         hipStreamWaitEvent(s, dc->join[a], 0) != hipSuccess)
       return HDA_E_DEVICE;
   }
+  rc = launch_overflow(d, pl, s);
+  if (rc != HDA_OK) return rc;
   return hipGetLastError() == hipSuccess ? HDA_OK : HDA_E_DEVICE;
 }
 
@@ -379,7 +480,7 @@ int hda_replay_per_heap(const hda_batch_desc* d, void* stream) {
   if (d->n_heaps == 0) return HDA_OK;
   if (!d->workspace || d->workspace_bytes < pl.bytes) return HDA_E_RANGE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (!set_lds_attr(pl.shape, pl.lds_group)) return HDA_E_DEVICE;
+  if (!set_lds_attrs(pl)) return HDA_E_DEVICE;
   int rc = classify(d, pl, s);
   if (rc != HDA_OK) return rc;
   // the host needs each heap's algorithm to pick the kernel it launches
@@ -390,15 +491,17 @@ int hda_replay_per_heap(const hda_batch_desc* d, void* stream) {
       hipStreamSynchronize(s) != hipSuccess)
     return HDA_E_DEVICE;
   for (int a = 0; a < 4; ++a) {
-    ReplayParams p = replay_params(d, pl, a);
+    ReplayParams p = replay_params(d, pl, pl.main, a, false);
     p.use_queue = 0;
     p.n_heaps = 1;
     for (uint32_t k = 0; k < counts[a]; ++k) {
       p.first = k;
-      if (launch(pl.shape->fn[a], dim3(1), dim3(64), pl.lds_group, s, p) != hipSuccess)
+      if (launch(pl.set->fn[a], dim3(1), dim3(64), pl.main.lds_group, s, p) != hipSuccess)
         return HDA_E_DEVICE;
     }
   }
+  rc = launch_overflow(d, pl, s);
+  if (rc != HDA_OK) return rc;
   return hipGetLastError() == hipSuccess ? HDA_OK : HDA_E_DEVICE;
 }
 

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "hda_core.h"
+#include "hda_lean.h"
 
 namespace hda {
 
@@ -26,6 +27,8 @@ struct ReplayParams {
   Ent* spill_free;       // per wave slot: cold free entries past LDS
   uint32_t* spill_stamp; // per wave slot: their stamps
   Ent* spill_live;       // per wave slot: cold live entries past LDS
+  int32_t* ovf_list;     // heaps that outgrew the lean tiers (lean kernels append)
+  uint32_t* ovf_count;   // their number
   int64_t n_heaps;       // heaps handled by this launch
   int64_t first;         // index into `order` of the first heap
   uint32_t cap_free, cap_live;   // total table capacities per heap
@@ -108,6 +111,59 @@ __device__ void replay_heap(const ReplayParams& p, const Cold& c, const HeapRegs
   if (lane == 0) p.status[heap] = st;
 }
 
+// Lean path (hda_lean.h).  Returns false when the tables outgrew the fast
+// tiers: then no state or status has been written, and the results written so
+// far are to be overwritten by a replay on the general path.
+template <int ALGO, int RF>
+__device__ bool lean_replay_heap(const ReplayParams& p, const LeanLds& lds, const HeapRegs& regs,
+                                 int64_t heap) {
+  const uint32_t lane = lane_id();
+  LeanHeap<ALGO, RF> w(lds, regs, p.cap_free, p.cap_live);
+  w.init();
+  int32_t st = 0;
+  const int64_t b0 = p.req_off[heap], b1 = p.req_off[heap + 1];
+  const uint64_t gm = (1ull << w.shift) - 1ull;
+  const int64_t last = b1 - 1;
+  int64_t nxt = b1 > b0 ? p.req[min<int64_t>(b0 + lane, last)] : 0;
+  for (int64_t base = b0; base < b1; base += 64) {
+    const int64_t q = nxt;
+    nxt = p.req[min<int64_t>(base + 64 + lane, last)];
+    const bool is_free = q < 0;
+    const bool big = q > w.arena;
+    uint32_t sg = (uint32_t)(((uint64_t)q + gm) >> w.shift);
+    sg = sg == 0u ? 1u : sg;
+    const uint32_t w0 = is_free ? (uint32_t)~(uint64_t)q : (big ? 0u : sg);
+    const uint32_t w1 = ceil_log2_u32(sg) + w.shift;
+    const uint64_t mfree = ballot(is_free);
+    const uint32_t n = (uint32_t)min<int64_t>(64, b1 - base);
+    uint32_t olo = 0, ohi = 0;
+    for (uint32_t j = 0; j < n; ++j) {
+      const uint32_t v0 = rdlane(w0, j);
+      int64_t r;
+      if ((mfree >> j) & 1ull) {
+        r = w.free_draw(v0);
+      } else if (v0 == 0u) {
+        r = kFail;
+      } else {
+        r = w.alloc(v0, ALGO == kSegFit ? rdlane(w1, j) : 0u);
+      }
+      if (r == kOverflow) return false;
+      if (r == kENoMeta && st == 0) st = (int32_t)kENoMeta;
+      olo = put_lane(olo, j, (uint32_t)(uint64_t)r);
+      ohi = put_lane(ohi, j, (uint32_t)((uint64_t)r >> 32));
+    }
+    if (base + lane < b1) p.res[base + lane] = (int64_t)(((uint64_t)ohi << 32) | olo);
+  }
+  if (p.state) {
+    const int64_t so = p.state_off[heap], cap = p.state_off[heap + 1] - so;
+    const int64_t need = w.dump(p.state + so, cap);
+    if (lane == 0) p.state_len[heap] = need;
+    if (need > cap && st == 0) st = (int32_t)kERange;
+  }
+  if (lane == 0) p.status[heap] = st;
+  return true;
+}
+
 // Heap with invalid parameters: every result and the status are E_INVAL.
 __device__ __forceinline__ void reject_heap(const ReplayParams& p, int64_t heap) {
   const uint32_t lane = lane_id();
@@ -130,6 +186,21 @@ __device__ __forceinline__ void replay_one_heap(const ReplayParams& p, const Col
     return;
   }
   replay_heap<ALGO, RF, RL>(p, c, h, heap);
+}
+
+// Lean replay of one heap known to use algorithm ALGO; a heap that outgrows
+// the fast tiers is appended to the overflow list.
+template <int ALGO, int RF>
+__device__ __forceinline__ void lean_one_heap(const ReplayParams& p, const LeanLds& lds,
+                                              int64_t heap) {
+  HeapRegs h;
+  if (!heap_params(p, heap, h) || h.algo != ALGO) {
+    reject_heap(p, heap);
+    return;
+  }
+  if (!lean_replay_heap<ALGO, RF>(p, lds, h, heap)) {
+    if (lane_id() == 0) p.ovf_list[atomicAdd(p.ovf_count, 1u)] = (int32_t)heap;
+  }
 }
 
 // Any algorithm (used where one program must serve every heap).

@@ -28,15 +28,19 @@ def lib():
         vp = ctypes.c_void_p
         u32 = ctypes.c_uint32
         L.emu_replay.restype = ctypes.c_int
-        L.emu_replay.argtypes = [ctypes.c_int64] + [vp] * 10 + [ctypes.c_int] + [u32] * 4 + [vp]
+        L.emu_replay.argtypes = [ctypes.c_int64] + [vp] * 10 + [ctypes.c_int] + [u32] * 4 + [vp, vp]
         _lib = L
     return _lib
 
 
-def replay(batch, kf=64, kl=64, cf=4096, cl=4096, shape=2):
+def replay(batch, kf=64, kl=64, cf=4096, cl=4096, shape=2, overflowed=None):
     """Replay a workloads.Batch heap by heap in the emulator.  shape selects
-    the register part: 0 none, 1 = (1, 2) chunks, 2 = (4, 8) chunks; kf/kl are
-    the cold entries kept in "LDS"; cf/cl the table capacities."""
+    the core: general with 0 = no register part, 1 = (1, 2) chunks, 2 = (4, 8)
+    chunks; lean with 3 = one, 4 = four free chunks in registers (kf/kl are
+    then its LDS entries, and a heap that outgrows them is replayed again on
+    the general core).  kf/kl are the cold entries kept in "LDS"; cf/cl the
+    table capacities.  overflowed, if given, is a uint8 array of heaps that
+    took the second pass."""
     H = batch.heaps
     P = lambda a: a.ctypes.data  # noqa: E731
     arena = np.ascontiguousarray(batch.arena, np.int64)
@@ -54,6 +58,7 @@ def replay(batch, kf=64, kl=64, cf=4096, cl=4096, shape=2):
     status = np.zeros(H, np.int32)
     syncs = np.zeros(H, np.uint64)
     lib().emu_replay(H, P(arena), P(align), P(algo), P(off), P(req), P(res), P(state),
-                     P(so), P(sl), P(status), int(shape), kf, kl, cf, cl, P(syncs))
+                     P(so), P(sl), P(status), int(shape), kf, kl, cf, cl, P(syncs),
+                     None if overflowed is None else P(overflowed))
     states = [state[so[h]:so[h] + sl[h]].copy() for h in range(H)]
     return res, states, status, syncs

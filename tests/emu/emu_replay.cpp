@@ -23,17 +23,30 @@ namespace {
 struct LaneJob {
   const ReplayParams* p;
   const Cold* c;
+  const LeanLds* lds;
   int64_t heap;
   int shape;
   int done;
 };
 LaneJob g_job;
 
+template <int RF>
+void lean_any(const ReplayParams& p, const LeanLds& lds, int64_t heap) {
+  switch (p.algo[heap]) {
+    case kFirstFit: lean_one_heap<kFirstFit, RF>(p, lds, heap); break;
+    case kNextFit: lean_one_heap<kNextFit, RF>(p, lds, heap); break;
+    case kBestFit: lean_one_heap<kBestFit, RF>(p, lds, heap); break;
+    default: lean_one_heap<kSegFit, RF>(p, lds, heap); break;
+  }
+}
+
 void lane_main() {
   switch (g_job.shape) {
     case 0: replay_any_heap<0, 0>(*g_job.p, *g_job.c, g_job.heap); break;
     case 1: replay_any_heap<1, 2>(*g_job.p, *g_job.c, g_job.heap); break;
-    default: replay_any_heap<4, 8>(*g_job.p, *g_job.c, g_job.heap); break;
+    case 2: replay_any_heap<4, 8>(*g_job.p, *g_job.c, g_job.heap); break;
+    case 3: lean_any<1>(*g_job.p, *g_job.lds, g_job.heap); break;
+    default: lean_any<4>(*g_job.p, *g_job.lds, g_job.heap); break;
   }
   // a finished lane keeps handing over until every lane has finished
   g_job.done++;
@@ -47,22 +60,45 @@ void lane_main() {
   }
 }
 
-const int kShapeRF[] = {0, 1, 4}, kShapeRL[] = {0, 2, 8};
+const int kShapeRF[] = {0, 1, 4, 0, 0}, kShapeRL[] = {0, 2, 8, 0, 0};
+
+// Run one heap as a wave of 64 fibers.
+void run_wave(EmuWave& w, std::vector<std::vector<uint8_t>>& stacks) {
+  w.syncs = 0;
+  for (int l = 0; l < 64; ++l) {
+    getcontext(&w.lane_ctx[l]);
+    w.lane_ctx[l].uc_stack.ss_sp = stacks[l].data();
+    w.lane_ctx[l].uc_stack.ss_size = stacks[l].size();
+    w.lane_ctx[l].uc_link = nullptr;
+    makecontext(&w.lane_ctx[l], lane_main, 0);
+  }
+  emu_lane = 0;
+  swapcontext(&w.main_ctx, &w.lane_ctx[0]);
+}
 
 }  // namespace
 
-// shape: 0 = no register part, 1 = (1, 2) chunks, 2 = (4, 8) chunks in
-// registers.  kf/kl: cold entries in "LDS"; cap_free/cap_live: capacities.
+// shape: general core with 0 = no register part, 1 = (1, 2) chunks, 2 = (4, 8)
+// chunks in registers; lean core with 3 = one, 4 = four free chunks in
+// registers, where a heap that outgrows its tiers is replayed again by the
+// general core with no register part (overflowed[h] = 1).  kf/kl: entries in
+// "LDS"; cap_free/cap_live: capacities.
 extern "C" int emu_replay(int64_t H, const int64_t* arena, const int64_t* align,
                           const int32_t* algo, const int64_t* req_off, const int64_t* req,
                           int64_t* res, int64_t* state, const int64_t* state_off,
                           int64_t* state_len, int32_t* status, int shape, uint32_t kf,
-                          uint32_t kl, uint32_t cap_free, uint32_t cap_live, uint64_t* syncs) {
+                          uint32_t kl, uint32_t cap_free, uint32_t cap_live, uint64_t* syncs,
+                          uint8_t* overflowed) {
   ReplayParams p;
   std::memset(&p, 0, sizeof(p));
   p.arena = arena; p.align = align; p.algo = algo; p.req_off = req_off; p.req = req;
   p.res = res; p.state = state; p.state_off = state_off; p.state_len = state_len;
   p.status = status;
+  const bool lean = shape >= 3;
+  const uint32_t lean_rf = shape == 3 ? 1u : 4u;
+  // lean tiers: LDS entries beyond the register chunks
+  const uint32_t lkf = kf, lkl = kl;
+  if (lean) { kf = 64; kl = 128; shape = 0; }  // general tiers of the second pass
   const uint32_t hf = 64u * kShapeRF[shape], hl = 64u * kShapeRL[shape];
   const uint32_t coldF = cap_free > hf ? cap_free - hf : 0u;
   const uint32_t coldL = cap_live > hl ? cap_live - hl : 0u;
@@ -71,6 +107,11 @@ extern "C" int emu_replay(int64_t H, const int64_t* arena, const int64_t* align,
   p.cap_free = cap_free; p.cap_live = cap_live;
   p.kf = kf; p.kl = kl; p.sf = coldF - kf; p.sl = coldL - kl;
   std::vector<uint8_t> lds(size_t(kf) * 12 + size_t(kl) * 8 + 16);
+  std::vector<uint8_t> llds(size_t(lkf) * 12 + size_t(lkl) * 8 + 16);
+  std::vector<int32_t> ovf_list(H + 1);
+  uint32_t ovf_count = 0;
+  p.ovf_list = ovf_list.data();
+  p.ovf_count = &ovf_count;
   std::vector<Ent> gf(p.sf + 64), gl(p.sl + 64);
   std::vector<uint32_t> gst(p.sf + 64);
   const size_t stack_bytes = 256 * 1024;
@@ -88,18 +129,31 @@ extern "C" int emu_replay(int64_t H, const int64_t* arena, const int64_t* align,
     c.ll = reinterpret_cast<Ent*>(lds.data() + size_t(kf) * 12);
     c.gf = gf.data(); c.gst = gst.data(); c.gl = gl.data();
     c.kf = kf; c.kl = kl; c.cf = coldF; c.cl = coldL;
-    g_job = LaneJob{&p, &c, h, shape, 0};
-    w.syncs = 0;
-    for (int l = 0; l < 64; ++l) {
-      getcontext(&w.lane_ctx[l]);
-      w.lane_ctx[l].uc_stack.ss_sp = stacks[l].data();
-      w.lane_ctx[l].uc_stack.ss_size = stack_bytes;
-      w.lane_ctx[l].uc_link = nullptr;
-      makecontext(&w.lane_ctx[l], lane_main, 0);
+    uint64_t n_sync = 0;
+    if (lean) {
+      std::memset(llds.data(), 0xA5, llds.size());
+      LeanLds ll;
+      ll.cf = reinterpret_cast<Ent*>(llds.data());
+      ll.ck = reinterpret_cast<uint32_t*>(llds.data() + size_t(lkf) * 8);
+      ll.lv = reinterpret_cast<Ent*>(llds.data() + size_t(lkf) * 12);
+      ll.kf = lkf;
+      ll.kl = lkl;
+      const uint32_t before = ovf_count;
+      g_job = LaneJob{&p, &c, &ll, h, lean_rf == 1 ? 3 : 4, 0};
+      run_wave(w, stacks);
+      n_sync += w.syncs;
+      if (overflowed) overflowed[h] = ovf_count != before;
+      if (ovf_count != before) {  // second pass on the general core
+        g_job = LaneJob{&p, &c, nullptr, h, 0, 0};
+        run_wave(w, stacks);
+        n_sync += w.syncs;
+      }
+    } else {
+      g_job = LaneJob{&p, &c, nullptr, h, shape, 0};
+      run_wave(w, stacks);
+      n_sync = w.syncs;
     }
-    emu_lane = 0;
-    swapcontext(&w.main_ctx, &w.lane_ctx[0]);
-    if (syncs) syncs[h] = w.syncs;
+    if (syncs) syncs[h] = n_sync;
   }
   emu_wave = nullptr;
   return 0;

@@ -15,3 +15,10 @@ struct uint2 {
 inline uint2 make_uint2(uint32_t x, uint32_t y) { return uint2{x, y}; }
 using std::max;
 using std::min;
+
+// one heap runs at a time on one host thread: a plain read-modify-write
+inline uint32_t atomicAdd(uint32_t* p, uint32_t v) {
+  const uint32_t o = *p;
+  *p = o + v;
+  return o;
+}

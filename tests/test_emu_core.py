@@ -92,3 +92,79 @@ def test_invalid_heap_parameters():
     assert status.tolist() == [0, -2, 0]
     assert (res[b.req_off[1]:b.req_off[2]] == -2).all()
     check(b, res, states, status, heaps=[0, 2])
+
+
+# ---- lean core (registers + LDS, second pass on the general core) ----
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_lean_single_heap_64KiB(algo):
+    b = W.single_heap(n=4000).with_algo(algo)
+    ovf = np.zeros(b.heaps, np.uint8)
+    res, states, status, _ = emu.replay(b, kf=128, kl=1024, cf=4096, cl=8192, shape=4,
+                                        overflowed=ovf)
+    check(b, res, states, status)
+    assert not ovf.any()
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_lean_16MiB_heap_cold_entries_in_lds(algo):
+    """One register chunk: most free entries live in LDS."""
+    b = W.uniform_batch(heaps=1, n=2500, algo=algo)
+    ovf = np.zeros(b.heaps, np.uint8)
+    res, states, status, _ = emu.replay(b, kf=512, kl=1024, cf=4096, cl=4096, shape=3,
+                                        overflowed=ovf)
+    check(b, res, states, status)
+    assert not ovf.any()
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_lean_overflow_replays_on_general_core(algo):
+    """Tiers far smaller than the tables: the heap stops on the lean core and
+    is replayed from the start on the general core, with the same results."""
+    b = W.uniform_batch(heaps=1, n=2000, algo=algo)
+    ovf = np.zeros(b.heaps, np.uint8)
+    res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=4096, cl=4096, shape=3,
+                                        overflowed=ovf)
+    check(b, res, states, status)
+    assert ovf.all()
+
+
+def test_lean_capacity_within_tiers_is_exact():
+    """Capacities no larger than the tiers: E_NOMETA on the lean core itself,
+    no second pass, results equal to the general core's."""
+    b = W.uniform_batch(heaps=1, n=1500, algo=2)
+    ovf = np.zeros(b.heaps, np.uint8)
+    res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=64, cl=64, shape=3,
+                                        overflowed=ovf)
+    gres, gstates, gstatus, _ = emu.replay(b, kf=64, kl=64, cf=64, cl=64, shape=1)
+    assert not ovf.any()
+    assert status[0] == -4 == gstatus[0]
+    assert np.array_equal(res, gres)
+    assert np.array_equal(states[0], gstates[0])
+
+
+def test_lean_random_small_heaps():
+    rng = np.random.default_rng(11)
+    parts = []
+    for h in range(40):
+        gran = int(rng.integers(1, 400))
+        parts.append(W.random_tiny(int(rng.integers(1 << 30)), int(rng.integers(0, 400)),
+                                   gran, align=int(1 << rng.integers(0, 12)),
+                                   algo=int(rng.integers(0, 4)),
+                                   max_granules=max(1, gran // int(rng.integers(1, 8)))))
+    b = W.concat(parts)
+    ovf = np.zeros(b.heaps, np.uint8)
+    res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=512, cl=512, shape=3,
+                                        overflowed=ovf)
+    check(b, res, states, status)
+
+
+def test_lean_invalid_heap_parameters():
+    good = W.random_tiny(1, 50, 32, align=16)
+    bad = W.random_tiny(2, 40, 8, align=16)
+    bad.arena[:] = 1000
+    b = W.concat([good, bad, good])
+    res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=256, cl=256, shape=4)
+    assert status.tolist() == [0, -2, 0]
+    assert (res[b.req_off[1]:b.req_off[2]] == -2).all()
+    check(b, res, states, status, heaps=[0, 2])

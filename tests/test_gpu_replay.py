@@ -87,13 +87,16 @@ def test_16MiB_heaps_reduced(algo):
 
 
 SPILL_TUNINGS = {
-    "lds64": hda.tuning(heaps_per_group=2, reg_free=-1, reg_live=-1, lds_free=64, lds_live=64),
-    "regs_then_device": hda.tuning(heaps_per_group=2, reg_free=2, reg_live=4, lds_free=-1,
-                                   lds_live=-1),
-    "regs_lds_device": hda.tuning(heaps_per_group=4, reg_free=2, reg_live=4, lds_free=64,
-                                  lds_live=64),
-    "free_regs_live_lds": hda.tuning(heaps_per_group=4, reg_free=6, reg_live=-1, lds_free=64,
-                                     lds_live=128),
+    # general core: LDS, then device memory
+    "general_lds64": hda.tuning(heaps_per_group=2, reg_free=-1, reg_live=-1, lds_free=64,
+                                lds_live=64),
+    "general_no_lds": hda.tuning(heaps_per_group=4, reg_free=-1, reg_live=-1, lds_free=-1,
+                                 lds_live=-1),
+    # lean core with tiers too small for these heaps: every heap outgrows
+    # them and is replayed again on the general core
+    "lean_overflow": hda.tuning(heaps_per_group=2, reg_free=4, lds_free=-1, lds_live=64),
+    "lean6_overflow": hda.tuning(heaps_per_group=4, reg_free=6, reg_live=-1, lds_free=64,
+                                 lds_live=128),
 }
 
 
@@ -112,9 +115,9 @@ def test_tuning_does_not_change_results():
     b = W.concat([c2_like(16, 8000, a) for a in ALGOS], "mixed")
     ref = None
     for tu in (hda.tuning(), hda.tuning(heaps_per_group=1, reg_free=-1, reg_live=-1),
-               hda.tuning(heaps_per_group=8, reg_free=2, reg_live=4, lds_free=128, lds_live=256),
+               hda.tuning(heaps_per_group=8, reg_free=-1, lds_free=128, lds_live=256),
                hda.tuning(heaps_per_group=16, lds_free=64, lds_live=512, groups=3),
-               hda.tuning(heaps_per_group=2, reg_free=4, reg_live=8, lds_free=-1, lds_live=-1,
+               hda.tuning(heaps_per_group=2, reg_free=4, lds_free=-1, lds_live=64,
                           groups=1),
                hda.tuning(heaps_per_group=4, reg_free=6, reg_live=-1, lds_live=2048)):
         say("case: tuning", tu)
@@ -128,11 +131,13 @@ def test_tuning_does_not_change_results():
             assert all(np.array_equal(x, y) for x, y in zip(states, ref[1]))
 
 
-def test_per_heap_launch_matches_batched():
+@pytest.mark.parametrize("where", ("default", "lean_overflow"))
+def test_per_heap_launch_matches_batched(where):
     b = W.concat([c2_like(6, 5000, a) for a in ALGOS], "mixed")
-    say("case: per-heap launches, 24 heaps")
-    r1, s1, st1 = gpu_replay(b)
-    r2, s2, st2 = gpu_replay(b, per_heap=True)
+    tu = hda.tuning() if where == "default" else SPILL_TUNINGS[where]
+    say(f"case: per-heap launches, 24 heaps, tuning {where}")
+    r1, s1, st1 = gpu_replay(b, tuning=tu)
+    r2, s2, st2 = gpu_replay(b, tuning=tu, per_heap=True)
     assert np.array_equal(r1, r2)
     assert all(np.array_equal(x, y) for x, y in zip(s1, s2))
     check_against_oracle(b, r2, s2, st2)
@@ -147,6 +152,16 @@ def test_uneven_batch_reduced():
     heaps = sorted(set(rng.choice(b.heaps, 200, replace=False).tolist())
                    | set(np.argsort(-lens)[:8].tolist()))
     check_against_oracle(b, res, states, status, heaps)
+
+
+@pytest.mark.parametrize("bad", (dict(reg_free=3), dict(reg_live=4), dict(lds_free=100),
+                                 dict(heaps_per_group=17), dict(lds_live=1 << 20)))
+def test_bad_tuning_is_rejected(bad):
+    db = hda.upload(c2_like(2, 100, 0), tuning=(0,) * 6)
+    db.tuning = hda.tuning(**bad)
+    with pytest.raises(hda.HdaError) as e:
+        hda.hda_replay_resolve(db)
+    assert e.value.code == hda.HDA_E_INVAL
 
 
 def test_bad_heap_parameters():
