@@ -10,7 +10,9 @@ Inputs are synthetic (seeded) and resident in HBM before timing starts.
 
 Printed: one JSON line with ops/s (value), the per-heap-launch baseline on a
 sample of heaps, the replay kernel's roofline figures measured with HIP events
-on its stream, and the CPU oracle timed on a bounded sample.
+on its stream, the p50/p99 request latency of the device-resident service
+under an open-loop load (100,000 clients, 1e7 requests/s offered), and the
+CPU oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 2]
 """
@@ -88,6 +90,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1024,
                     help="heaps per algorithm replayed by the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=1e7,
+                    help="serving leg: open-loop arrivals per second (0 = skip)")
+    ap.add_argument("--serve-clients", type=int, default=100_000)
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="serving leg: measured window (after 0.5 s of warmup)")
     ap.add_argument("--tuning", type=str, default="0,0,0,0,0,0",
                     help="heaps_per_group,reg_free,reg_live,lds_free,lds_live,groups "
                          "(0 = default, -1 = none)")
@@ -188,6 +195,29 @@ def main():
     per_heap_value = ph_ops / ph_time
     log(f"[bench] per-heap launches: {per_heap_value / 1e6:.2f} M ops/s on {S} heaps/algo")
 
+    serving = None
+    if args.serve_rate > 0:
+        # device-resident service: one heap per client (64 MiB-4 GiB, 512 B
+        # alignment, segregated fit), Poisson arrivals, 70 % power-of-two sizes
+        # 512 B-256 MiB and 30 % log-uniform, exponential lifetimes (mean 500
+        # requests); latency from submission to completion seen by the client
+        srv = hda.Server(max_heaps=args.serve_clients + 16, max_seconds=600)
+        try:
+            rep, _ = srv.load(clients=args.serve_clients, rate=args.serve_rate, warmup_s=0.5,
+                              measure_s=args.serve_seconds, threads=8)
+        finally:
+            srv.stop()
+        if rep["errors"]:
+            raise RuntimeError(f"serving leg reported {rep['errors']} errors")
+        serving = {"offered_rate": args.serve_rate, "clients": args.serve_clients,
+                   "throughput": rep["throughput"], "unit": "requests/s",
+                   "p50_us": rep["p50_us"], "p99_us": rep["p99_us"],
+                   "p999_us": rep["p999_us"], "max_us": rep["max_us"],
+                   "window_s": rep["window_s"], "completed": rep["completed"],
+                   "alloc_fail": rep["alloc_fail"]}
+        log(f"[bench] serving at {args.serve_rate:.3g}/s: {rep['throughput']:.3g}/s, "
+            f"p50 {rep['p50_us']:.1f} us, p99 {rep['p99_us']:.1f} us")
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -240,6 +270,7 @@ def main():
                      "avg_launch_ms": avg_launch_s * 1e3,
                      "bytes_per_request": BYTES_PER_REQUEST,
                      "requests_per_launch": batch.requests},
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -77,8 +77,8 @@ enum {
  *     len_k, then the block addresses from list head to tail.
  */
 /* Where each heap's tables live.  Default (lean) path: the first
- * 64*reg_free free-table entries are held in vector registers (reg_free = 4
- * or 6; 0 = 4), the next lds_free free entries and lds_live live entries in
+ * 64*reg_free free-table entries are held in vector registers (reg_free = 4;
+ * 0 = 4), the next lds_free free entries and lds_live live entries in
  * LDS (defaults 128 and 1024).  A heap whose tables outgrow these tiers
  * before reaching meta_free / meta_live is replayed again from its first
  * request on the general path, inside the same call; results do not depend

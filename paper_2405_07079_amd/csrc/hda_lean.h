@@ -139,12 +139,27 @@ struct LeanHeap {
     m.lv[i] = mk_ent(a, s);  // every lane, same value (see write())
   }
 
-  // Visit every chunk holding entries: f(chunk, a, s, key).
+  // Visit every chunk holding entries: f(chunk, a, s, key).  LDS chunks are
+  // loaded four at a time before any is used, so their latencies overlap.
   template <typename Fn>
   __device__ __forceinline__ void scan(Fn&& f) {
 #pragma unroll
     for (int k = 0; k < RF; ++k) f((uint32_t)k, fa[k], fs[k], kSeg ? fk[k] : 0u);
-    for (uint32_t c = RF; 64u * c < F; ++c) {
+    uint32_t c = RF;
+    for (; 64u * (c + 3u) < F; c += 4u) {
+      const uint32_t i = 64u * (c - RF) + lane_id();
+      wave_sync();
+      Ent e[4];
+      uint32_t k[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        e[u] = m.cf[i + 64u * u];
+        k[u] = kSeg ? m.ck[i + 64u * u] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) f(c + u, ent_a(e[u]), ent_s(e[u]), k[u]);
+    }
+    for (; 64u * c < F; ++c) {
       const uint32_t i = 64u * (c - RF) + lane_id();
       wave_sync();
       const Ent e = m.cf[i];

@@ -187,7 +187,7 @@ struct KernelSet {
 const KernelSet kSets[] = {
     {0, {(const void*)general_kernel<kFirstFit>, (const void*)general_kernel<kNextFit>,
          (const void*)general_kernel<kBestFit>, (const void*)general_kernel<kSegFit>}},
-    HDA_LEAN(4), HDA_LEAN(6)};
+    HDA_LEAN(4)};
 #undef HDA_LEAN
 constexpr int kDefaultRF = 4;
 

@@ -1,0 +1,86 @@
+"""The 256 GiB segregated-fit heap (one wavefront, 50 M requests) on the GPU.
+
+Its tables peak at about 2,100 free and 13,300 live blocks, so the call asks
+for capacities of 4,096 / 16,384 and keeps both tables in one wave's LDS
+(1,920 free entries past the four register chunks, 16,384 live entries).
+
+The prefix test compares every result and the final state with the oracle.
+The full-length test (HDA_FULL_SIZE=1; about a minute of GPU time) compares
+digests of all 50 M results and of the final state, and sampled results,
+with tests/golden/large_seg_fit_256GiB.json, written from the oracle by
+tests/golden/make_golden.py.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+import oracle  # noqa: E402
+from paper_2405_07079_amd import hda  # noqa: E402
+from paper_2405_07079_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TUNING = hda.tuning(heaps_per_group=1, reg_free=4, lds_free=1920, lds_live=16384)
+META_FREE, META_LIVE = 4096, 16384
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def digest(a):
+    return hashlib.sha256(np.ascontiguousarray(a, "<i8").tobytes()).hexdigest()
+
+
+def prefix(b, n):
+    return W.Batch(b.name, b.arena, b.align, b.algo, np.array([0, n], np.int64),
+                   np.ascontiguousarray(b.req[:n]), dict(b.meta))
+
+
+def run(batch):
+    db = hda.upload(batch, tuning=TUNING, meta_free=META_FREE, meta_live=META_LIVE)
+    assert hda.hda_replay_resolve(db)["lds_live"] == 16384
+    hda.hda_replay(db)
+    torch.cuda.synchronize()
+    return db.res.cpu().numpy(), hda.states_to_host(db)[0], int(db.status[0].item())
+
+
+@pytest.fixture(scope="module")
+def large():
+    return W.large_seg_fit()
+
+
+def test_large_seg_fit_prefix(large):
+    n = 2_000_000
+    b = prefix(large, n)
+    say(f"case: 256 GiB segregated fit, first {n} requests")
+    res, st, status = run(b)
+    ores, ost = oracle.replay_heap(W.SEG_FIT, int(b.arena[0]), int(b.align[0]), b.req)
+    assert status == 0
+    if not np.array_equal(res, ores):
+        i = int(np.nonzero(res != ores)[0][0])
+        raise AssertionError(f"request {i}: gpu {res[i]} oracle {ores[i]}")
+    assert np.array_equal(st, ost)
+
+
+@pytest.mark.skipif(os.environ.get("HDA_FULL_SIZE") != "1",
+                    reason="full 50 M-request run: set HDA_FULL_SIZE=1")
+def test_large_seg_fit_full_length(large):
+    with open(os.path.join(HERE, "golden", "large_seg_fit_256GiB.json")) as f:
+        g = json.load(f)
+    assert digest(large.req) == g["trace_sha256"]
+    say("case: 256 GiB segregated fit, 50 M requests")
+    res, st, status = run(large)
+    assert status == 0
+    pos = np.array(g["sample_positions"])
+    assert np.array_equal(res[pos], np.array(g["sample_results"]))
+    parsed = oracle.parse_state(st, W.SEG_FIT)
+    assert len(parsed["free"]) == g["final_free_blocks"]
+    assert len(parsed["live"]) == g["final_live_blocks"]
+    assert digest(res) == g["results_sha256"]
+    assert digest(st) == g["state_sha256"]

@@ -95,8 +95,8 @@ SPILL_TUNINGS = {
     # lean core with tiers too small for these heaps: every heap outgrows
     # them and is replayed again on the general core
     "lean_overflow": hda.tuning(heaps_per_group=2, reg_free=4, lds_free=-1, lds_live=64),
-    "lean6_overflow": hda.tuning(heaps_per_group=4, reg_free=6, reg_live=-1, lds_free=64,
-                                 lds_live=128),
+    "lean_lds_overflow": hda.tuning(heaps_per_group=4, reg_free=4, reg_live=-1, lds_free=64,
+                                    lds_live=128),
 }
 
 
@@ -119,7 +119,7 @@ def test_tuning_does_not_change_results():
                hda.tuning(heaps_per_group=16, lds_free=64, lds_live=512, groups=3),
                hda.tuning(heaps_per_group=2, reg_free=4, lds_free=-1, lds_live=64,
                           groups=1),
-               hda.tuning(heaps_per_group=4, reg_free=6, reg_live=-1, lds_live=2048)):
+               hda.tuning(heaps_per_group=4, reg_free=4, reg_live=-1, lds_live=2048)):
         say("case: tuning", tu)
         res, states, status = gpu_replay(b, tuning=tu)
         assert (status == 0).all()
@@ -154,7 +154,8 @@ def test_uneven_batch_reduced():
     check_against_oracle(b, res, states, status, heaps)
 
 
-@pytest.mark.parametrize("bad", (dict(reg_free=3), dict(reg_live=4), dict(lds_free=100),
+@pytest.mark.parametrize("bad", (dict(reg_free=3), dict(reg_free=6), dict(reg_live=4),
+                                 dict(lds_free=100),
                                  dict(heaps_per_group=17), dict(lds_live=1 << 20)))
 def test_bad_tuning_is_rejected(bad):
     db = hda.upload(c2_like(2, 100, 0), tuning=(0,) * 6)
