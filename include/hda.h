@@ -80,9 +80,9 @@ enum {
  * 64*reg_free free-table entries are held in vector registers (reg_free = 4;
  * 0 = 4), the next lds_free free entries and lds_live live entries in
  * LDS (defaults 128 and 1024).  A heap whose tables outgrow these tiers
- * before reaching meta_free / meta_live is replayed again from its first
- * request on the general path, inside the same call; results do not depend
- * on the tuning.  reg_free = -1 selects the general path for every heap: no
+ * before reaching meta_free / meta_live moves them, mid-trace, into the
+ * general path's layout (LDS, then device memory in the workspace) and
+ * continues there; results do not depend on the tuning.  reg_free = -1 selects the general path for every heap: no
  * registers, lds_free / lds_live entries in LDS (defaults 64 and 1024), the
  * rest in device memory (workspace).  reg_live must be 0 or -1 (the live
  * table is never held in registers).  0 = default for every field; -1 = none

@@ -11,9 +11,10 @@
 // with no bounds mask.
 //
 // When a table would outgrow these tiers before it reaches the capacity the
-// caller asked for, the heap stops with kOverflow and is replayed from its
-// first request by the general core (hda_core.h), whose tables spill to
-// device memory.  Results are the same on both paths.
+// caller asked for, the request stops with kOverflow (changing nothing), the
+// tables move into the general core's layout (hda_core.h, whose tables
+// continue into device memory) and the heap goes on there.  Results are the
+// same on both paths.
 //
 // Same rules as the general core: values that feed a cross-lane operation are
 // never produced under a lane-dependent branch, and every LDS access is
@@ -373,6 +374,46 @@ struct LeanHeap {
   __device__ __forceinline__ int64_t free_draw(uint32_t r) {
     if (L == 0u) return kFail;
     return free_index((uint32_t)(((uint64_t)r * (uint64_t)L) >> 32));
+  }
+
+  // Hand this heap over to the general core (hda_core.h, no register
+  // chunks) built on the same LDS bytes: general free entry i is LDS slot i
+  // while i < kf and device slot i - kf after, with its push stamp beside it;
+  // the live table is already where the general core keeps it.  Free entry i
+  // moves from lean LDS slot i - 64*RF (or a register chunk) to general slot
+  // i, i.e. towards higher LDS slots, so chunks are moved last first.
+  __device__ void migrate(const Cold& c, HeapRegs& h) {
+    const uint32_t lane = lane_id();
+    const uint32_t nch = (F + 63u) >> 6;
+    for (uint32_t ch = nch; ch-- > (uint32_t)RF;) {
+      const uint32_t src = 64u * (ch - RF) + lane, gi = 64u * ch + lane;
+      wave_sync();
+      const Ent e = m.cf[src];
+      const uint32_t st = kSeg ? m.ck[src] & (kStampLimit - 1u) : 0u;
+      wave_sync();
+      if (gi < F) put_free(c, gi, e, st);
+    }
+#pragma unroll
+    for (int k = RF - 1; k >= 0; --k) {
+      const uint32_t gi = 64u * (uint32_t)k + lane;
+      wave_sync();
+      if (gi < F) put_free(c, gi, mk_ent(fa[k], fs[k]), kSeg ? fk[k] & (kStampLimit - 1u) : 0u);
+    }
+    wave_sync();
+    h.F = F;
+    h.L = L;
+    h.rover = rover;
+    h.clock = clock;
+    h.cnt = cnt;
+  }
+  __device__ static __forceinline__ void put_free(const Cold& c, uint32_t gi, Ent e, uint32_t st) {
+    if (gi < c.kf) {
+      c.lf[gi] = e;
+      if (kSeg) c.lst[gi] = st;
+    } else {
+      c.gf[gi - c.kf] = e;
+      if (kSeg) c.gst[gi - c.kf] = st;
+    }
   }
 
   // Canonical state, same format as the general core (hda.h).

@@ -27,10 +27,10 @@ using namespace hda;
 namespace {
 
 constexpr int kClasses = 5;  // four algorithms + invalid
-// Queue words in the workspace: one per algorithm, then the overflow pass's
-// queue and the overflow count.
-constexpr int kQueueWords = 6;
-constexpr int kOvfQueue = 4, kOvfCount = 5;
+// Queue words in the workspace: one per algorithm, then the number of heaps
+// moved from the lean to the general core.
+constexpr int kQueueWords = 5;
+constexpr int kMigrated = 4;
 
 struct ClassifyParams {
   const int64_t* arena;
@@ -149,17 +149,6 @@ __global__ void __launch_bounds__(1024) general_kernel(ReplayParams p) {
   for_each_heap(p, slot, [&](int64_t heap) __attribute__((always_inline)) { replay_one_heap<ALGO, 0, 0>(p, c, heap); });
 }
 
-// Second pass of the lean path: heaps of any algorithm that outgrew the lean
-// tiers, replayed from the start on the general path.
-__global__ void __launch_bounds__(1024) overflow_kernel(ReplayParams p) {
-  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  const uint32_t wave = uniform(threadIdx.x >> 6);  // the same in every lane of the wave
-  HDA_LDS uint8_t* mine = (HDA_LDS uint8_t*)smem + (size_t)wave * p.lds_wave_bytes;
-  const uint64_t slot = (uint64_t)blockIdx.x * p.waves_per_group + wave;
-  const Cold c = general_tiers(p, mine, slot);
-  for_each_heap(p, slot, [&](int64_t heap) __attribute__((always_inline)) { replay_any_heap<0, 0>(p, c, heap); });
-}
-
 // Lean-path kernel for one algorithm with RF free-table chunks in VGPRs.
 template <int ALGO, int RF>
 __global__ void __launch_bounds__(1024) lean_kernel(ReplayParams p) {
@@ -173,7 +162,12 @@ __global__ void __launch_bounds__(1024) lean_kernel(ReplayParams p) {
   lds.lv = (HDA_LDS Ent*)(mine + (size_t)p.kf * 12);
   lds.kf = p.kf;
   lds.kl = p.kl;
-  for_each_heap(p, slot, [&](int64_t heap) __attribute__((always_inline)) { lean_one_heap<ALGO, RF>(p, lds, heap); });
+  // the general core's tiers for a heap that outgrows the lean ones: the same
+  // LDS bytes, then this wave's spill slot
+  const Cold c = general_tiers(p, mine, slot);
+  for_each_heap(p, slot, [&](int64_t heap) __attribute__((always_inline)) {
+    lean_one_heap<ALGO, RF>(p, lds, c, heap);
+  });
 }
 
 // Kernel sets: rf = free-table chunks in VGPRs (0 = general path).
@@ -233,8 +227,7 @@ DeviceCtx* device_ctx() {
 
 uint32_t round64(int64_t x) { return (uint32_t)((x + 63) / 64 * 64); }
 
-// Launch geometry and tiers of one pass (the main per-algorithm launches, or
-// the overflow pass of the lean path).
+// Launch geometry and tiers of the per-algorithm launches.
 struct Pass {
   uint32_t W = 1, kf = 0, kl = 0, sf = 0, sl = 0, lds_wave = 0, lds_group = 0;
   int64_t groups[4] = {1, 1, 1, 1}, slots[4] = {1, 1, 1, 1};
@@ -245,8 +238,8 @@ struct Plan {
   const KernelSet* set;
   bool lean;
   uint32_t capF, capL;
-  Pass main, ovf;
-  size_t off_counts, off_queues, off_lists, off_ovf, bytes;
+  Pass main;
+  size_t off_counts, off_queues, off_lists, bytes;
 };
 
 int occupancy_groups(const void* fn, uint32_t W, uint32_t lds_group, int cus, int32_t want,
@@ -281,18 +274,18 @@ bool make_plan(const hda_batch_desc* d, bool persistent, Plan* pl) {
   if (!persistent) W = 1;
   const uint32_t capF = round64(d->meta_free > 0 ? d->meta_free : 4096);
   const uint32_t capL = round64(d->meta_live > 0 ? d->meta_live : 8192);
-  const uint32_t hotF = 64u * (uint32_t)rf;
-  const uint32_t coldF = capF > hotF ? capF - hotF : 0u;
   // LDS entries: 0 = default, -1 = none
   const uint32_t want_kf = tu.lds_free > 0 ? (uint32_t)tu.lds_free
                                            : (tu.lds_free < 0 ? 0u : (lean ? 128u : 64u));
   const uint32_t want_kl = tu.lds_live > 0 ? (uint32_t)tu.lds_live : (tu.lds_live < 0 ? 0u : 1024u);
   Pass& m = pl->main;
   m.W = W;
-  m.kf = std::min(want_kf, coldF);
+  // LDS parts never exceed the capacities; the general core (a lean heap
+  // after migration, too) keeps entries past them in device memory
+  m.kf = std::min(want_kf, capF);
   m.kl = std::min(want_kl, capL);
-  m.sf = lean ? 0u : coldF - m.kf;
-  m.sl = lean ? 0u : capL - m.kl;
+  m.sf = capF - m.kf;
+  m.sl = capL - m.kl;
   m.lds_wave = m.kf * 12u + m.kl * 8u;
   m.lds_group = m.lds_wave * W;
   if (m.lds_group > dc->max_lds) return false;
@@ -301,18 +294,6 @@ bool make_plan(const hda_batch_desc* d, bool persistent, Plan* pl) {
                                                 d->n_heaps)
                              : 1;
     m.slots[a] = m.groups[a] * W;
-  }
-  Pass& o = pl->ovf;
-  if (lean) {
-    o.W = 1;
-    o.kf = std::min(64u, capF);
-    o.kl = std::min(512u, capL);
-    o.sf = capF - o.kf;
-    o.sl = capL - o.kl;
-    o.lds_wave = o.kf * 12u + o.kl * 8u;
-    o.lds_group = o.lds_wave;
-    const int64_t g = std::max<int64_t>(1, std::min<int64_t>(2 * (int64_t)dc->cus, d->n_heaps));
-    for (int a = 0; a < 4; ++a) { o.groups[a] = a == 0 ? g : 0; o.slots[a] = a == 0 ? g : 0; }
   }
   pl->set = set;
   pl->lean = lean;
@@ -324,13 +305,11 @@ bool make_plan(const hda_batch_desc* d, bool persistent, Plan* pl) {
   pl->off_queues = off; off = align_up(off + kQueueWords * 4);
   const size_t H1 = (size_t)std::max<int64_t>(d->n_heaps, 1);
   pl->off_lists = off; off = align_up(off + (size_t)kClasses * H1 * 4);
-  pl->off_ovf = off; off = align_up(off + H1 * 4);
-  for (Pass* ps : {&pl->main, &pl->ovf})
-    for (int a = 0; a < 4; ++a) {
-      ps->off_free[a] = off; off = align_up(off + (size_t)ps->slots[a] * ps->sf * 8);
-      ps->off_stamp[a] = off; off = align_up(off + (size_t)ps->slots[a] * ps->sf * 4);
-      ps->off_live[a] = off; off = align_up(off + (size_t)ps->slots[a] * ps->sl * 8);
-    }
+  for (int a = 0; a < 4; ++a) {
+    m.off_free[a] = off; off = align_up(off + (size_t)m.slots[a] * m.sf * 8);
+    m.off_stamp[a] = off; off = align_up(off + (size_t)m.slots[a] * m.sf * 4);
+    m.off_live[a] = off; off = align_up(off + (size_t)m.slots[a] * m.sl * 8);
+  }
   pl->bytes = off;
   return true;
 }
@@ -356,9 +335,9 @@ ClassifyParams classify_params(const hda_batch_desc* d, const Plan& pl) {
   return q;
 }
 
-// Parameters of one launch: pass `ps`, algorithm a (or the overflow pass).
-ReplayParams replay_params(const hda_batch_desc* d, const Plan& pl, const Pass& ps, int a,
-                           bool overflow) {
+// Parameters of the launch for algorithm a.
+ReplayParams replay_params(const hda_batch_desc* d, const Plan& pl, int a) {
+  const Pass& ps = pl.main;
   ReplayParams p;
   std::memset(&p, 0, sizeof(p));
   p.arena = d->arena; p.align = d->align; p.algo = d->algo;
@@ -367,18 +346,10 @@ ReplayParams replay_params(const hda_batch_desc* d, const Plan& pl, const Pass& 
   p.status = d->status;
   uint8_t* ws = static_cast<uint8_t*>(d->workspace);
   uint32_t* queues = reinterpret_cast<uint32_t*>(ws + pl.off_queues);
-  int32_t* ovf = reinterpret_cast<int32_t*>(ws + pl.off_ovf);
-  if (overflow) {
-    p.list = ovf;
-    p.count = queues + kOvfCount;
-    p.queue = queues + kOvfQueue;
-  } else {
-    p.list = reinterpret_cast<const int32_t*>(ws + pl.off_lists) + (int64_t)a * d->n_heaps;
-    p.count = reinterpret_cast<const uint32_t*>(ws + pl.off_counts) + a;
-    p.queue = queues + a;
-  }
-  p.ovf_list = ovf;
-  p.ovf_count = queues + kOvfCount;
+  p.list = reinterpret_cast<const int32_t*>(ws + pl.off_lists) + (int64_t)a * d->n_heaps;
+  p.count = reinterpret_cast<const uint32_t*>(ws + pl.off_counts) + a;
+  p.queue = queues + a;
+  p.migrated = queues + kMigrated;
   p.spill_free = reinterpret_cast<Ent*>(ws + ps.off_free[a]);
   p.spill_stamp = reinterpret_cast<uint32_t*>(ws + ps.off_stamp[a]);
   p.spill_live = reinterpret_cast<Ent*>(ws + ps.off_live[a]);
@@ -401,7 +372,7 @@ bool set_lds_attr(const void* fn, uint32_t bytes) {
 bool set_lds_attrs(const Plan& pl) {
   for (int a = 0; a < 4; ++a)
     if (!set_lds_attr(pl.set->fn[a], pl.main.lds_group)) return false;
-  return !pl.lean || set_lds_attr((const void*)overflow_kernel, pl.ovf.lds_group);
+  return true;
 }
 
 hipError_t launch(const void* fn, dim3 grid, dim3 block, uint32_t lds, hipStream_t st,
@@ -414,16 +385,6 @@ int classify(const hda_batch_desc* d, const Plan& pl, hipStream_t s) {
   ClassifyParams q = classify_params(d, pl);
   hipLaunchKernelGGL(classify_kernel, dim3(1), dim3(1024), 0, s, q);
   return hipGetLastError() == hipSuccess ? HDA_OK : HDA_E_DEVICE;
-}
-
-// The lean path's second pass, on stream s after the main launches.
-int launch_overflow(const hda_batch_desc* d, const Plan& pl, hipStream_t s) {
-  if (!pl.lean) return HDA_OK;
-  ReplayParams p = replay_params(d, pl, pl.ovf, 0, true);
-  return launch((const void*)overflow_kernel, dim3((uint32_t)pl.ovf.groups[0]), dim3(64),
-                pl.ovf.lds_group, s, p) == hipSuccess
-             ? HDA_OK
-             : HDA_E_DEVICE;
 }
 
 }  // namespace
@@ -461,7 +422,7 @@ int hda_replay(const hda_batch_desc* d, void* stream) {
   if (rc != HDA_OK) return rc;
   if (hipEventRecord(dc->fork, s) != hipSuccess) return HDA_E_DEVICE;
   for (int a = 0; a < 4; ++a) {
-    ReplayParams p = replay_params(d, pl, pl.main, a, false);
+    ReplayParams p = replay_params(d, pl, a);
     if (hipStreamWaitEvent(dc->side[a], dc->fork, 0) != hipSuccess ||
         launch(pl.set->fn[a], dim3((uint32_t)pl.main.groups[a]), dim3(64 * pl.main.W),
                pl.main.lds_group, dc->side[a], p) != hipSuccess ||
@@ -469,8 +430,6 @@ int hda_replay(const hda_batch_desc* d, void* stream) {
         hipStreamWaitEvent(s, dc->join[a], 0) != hipSuccess)
       return HDA_E_DEVICE;
   }
-  rc = launch_overflow(d, pl, s);
-  if (rc != HDA_OK) return rc;
   return hipGetLastError() == hipSuccess ? HDA_OK : HDA_E_DEVICE;
 }
 
@@ -491,7 +450,7 @@ int hda_replay_per_heap(const hda_batch_desc* d, void* stream) {
       hipStreamSynchronize(s) != hipSuccess)
     return HDA_E_DEVICE;
   for (int a = 0; a < 4; ++a) {
-    ReplayParams p = replay_params(d, pl, pl.main, a, false);
+    ReplayParams p = replay_params(d, pl, a);
     p.use_queue = 0;
     p.n_heaps = 1;
     for (uint32_t k = 0; k < counts[a]; ++k) {
@@ -500,8 +459,6 @@ int hda_replay_per_heap(const hda_batch_desc* d, void* stream) {
         return HDA_E_DEVICE;
     }
   }
-  rc = launch_overflow(d, pl, s);
-  if (rc != HDA_OK) return rc;
   return hipGetLastError() == hipSuccess ? HDA_OK : HDA_E_DEVICE;
 }
 

@@ -27,8 +27,7 @@ struct ReplayParams {
   Ent* spill_free;       // per wave slot: cold free entries past LDS
   uint32_t* spill_stamp; // per wave slot: their stamps
   Ent* spill_live;       // per wave slot: cold live entries past LDS
-  int32_t* ovf_list;     // heaps that outgrew the lean tiers (lean kernels append)
-  uint32_t* ovf_count;   // their number
+  uint32_t* migrated;    // heaps moved from the lean to the general core, or null
   int64_t n_heaps;       // heaps handled by this launch
   int64_t first;         // index into `order` of the first heap
   uint32_t cap_free, cap_live;   // total table capacities per heap
@@ -55,36 +54,34 @@ __device__ __forceinline__ bool heap_params(const ReplayParams& p, int64_t heap,
   return true;
 }
 
-template <int ALGO, int RF, int RL>
-__device__ void replay_heap(const ReplayParams& p, const Cold& c, const HeapRegs& regs,
-                            int64_t heap) {
+// Run requests [from, to) of `heap` on core w (either core type).  Requests
+// are read 64 at a time (one per lane) and decoded by all lanes at once: a
+// free carries its draw, an allocation its size in granules (0 when larger
+// than the arena) and, for segregated fit, its byte class.  Loads are clamped
+// to the heap's last request instead of guarded by a lane-dependent branch,
+// since the values feed wave-wide reads.  Returns the position of the first
+// request not run: `to`, or the request that found the lean core's tiers too
+// small (it changed nothing, and the results before it are stored).
+template <int ALGO, typename Core>
+__device__ int64_t run_requests(const ReplayParams& p, Core& w, int64_t from, int64_t to,
+                                uint32_t shift, int64_t arena, int32_t& st) {
   const uint32_t lane = lane_id();
-  const uint32_t hot_f = 64u * RF, hot_l = 64u * RL;
-  const uint32_t capF = p.cap_free, capL = p.cap_live;
-  WaveHeap<ALGO, RF, RL> w(c, regs, capF, capL);
-  (void)hot_f; (void)hot_l;
-  w.init();
-  const int64_t b0 = p.req_off[heap], b1 = p.req_off[heap + 1];
-  const uint64_t gm = (1ull << w.h.shift) - 1ull;
-  // Requests are read 64 at a time (one per lane) and decoded by all lanes at
-  // once: a free carries its draw, an allocation its size in granules (0 when
-  // larger than the arena) and, for segregated fit, its byte class.  Loads are
-  // clamped to the heap's last request instead of guarded by a lane-dependent
-  // branch, since the values feed wave-wide reads.
-  const int64_t last = b1 - 1;
-  int64_t nxt = b1 > b0 ? p.req[min<int64_t>(b0 + lane, last)] : 0;
-  for (int64_t base = b0; base < b1; base += 64) {
+  const uint64_t gm = (1ull << shift) - 1ull;
+  const int64_t last = to - 1;
+  int64_t nxt = to > from ? p.req[min<int64_t>(from + lane, last)] : 0;
+  for (int64_t base = from; base < to; base += 64) {
     const int64_t q = nxt;
     nxt = p.req[min<int64_t>(base + 64 + lane, last)];
     const bool is_free = q < 0;
-    const bool big = q > w.h.arena;
-    uint32_t sg = (uint32_t)(((uint64_t)q + gm) >> w.h.shift);
+    const bool big = q > arena;
+    uint32_t sg = (uint32_t)(((uint64_t)q + gm) >> shift);
     sg = sg == 0u ? 1u : sg;
     const uint32_t w0 = is_free ? (uint32_t)~(uint64_t)q : (big ? 0u : sg);
-    const uint32_t w1 = ceil_log2_u32(sg) + w.h.shift;
+    const uint32_t w1 = ceil_log2_u32(sg) + shift;
     const uint64_t mfree = ballot(is_free);
-    const uint32_t n = (uint32_t)min<int64_t>(64, b1 - base);
+    const uint32_t n = (uint32_t)min<int64_t>(64, to - base);
     uint32_t olo = 0, ohi = 0;
+    uint32_t done = n;
     for (uint32_t j = 0; j < n; ++j) {
       const uint32_t v0 = rdlane(w0, j);
       int64_t r;
@@ -95,73 +92,61 @@ __device__ void replay_heap(const ReplayParams& p, const Cold& c, const HeapRegs
       } else {
         r = w.alloc(v0, ALGO == kSegFit ? rdlane(w1, j) : 0u);
       }
-      if (r == kENoMeta && w.h.status == 0) w.h.status = (int32_t)kENoMeta;
-      olo = put_lane(olo, j, (uint32_t)(uint64_t)r);
-      ohi = put_lane(ohi, j, (uint32_t)((uint64_t)r >> 32));
-    }
-    if (base + lane < b1) p.res[base + lane] = (int64_t)(((uint64_t)ohi << 32) | olo);
-  }
-  int32_t st = w.h.status;
-  if (p.state) {
-    const int64_t so = p.state_off[heap], cap = p.state_off[heap + 1] - so;
-    const int64_t need = w.dump(p.state + so, cap);
-    if (lane == 0) p.state_len[heap] = need;
-    if (need > cap && st == 0) st = (int32_t)kERange;
-  }
-  if (lane == 0) p.status[heap] = st;
-}
-
-// Lean path (hda_lean.h).  Returns false when the tables outgrew the fast
-// tiers: then no state or status has been written, and the results written so
-// far are to be overwritten by a replay on the general path.
-template <int ALGO, int RF>
-__device__ bool lean_replay_heap(const ReplayParams& p, const LeanLds& lds, const HeapRegs& regs,
-                                 int64_t heap) {
-  const uint32_t lane = lane_id();
-  LeanHeap<ALGO, RF> w(lds, regs, p.cap_free, p.cap_live);
-  w.init();
-  int32_t st = 0;
-  const int64_t b0 = p.req_off[heap], b1 = p.req_off[heap + 1];
-  const uint64_t gm = (1ull << w.shift) - 1ull;
-  const int64_t last = b1 - 1;
-  int64_t nxt = b1 > b0 ? p.req[min<int64_t>(b0 + lane, last)] : 0;
-  for (int64_t base = b0; base < b1; base += 64) {
-    const int64_t q = nxt;
-    nxt = p.req[min<int64_t>(base + 64 + lane, last)];
-    const bool is_free = q < 0;
-    const bool big = q > w.arena;
-    uint32_t sg = (uint32_t)(((uint64_t)q + gm) >> w.shift);
-    sg = sg == 0u ? 1u : sg;
-    const uint32_t w0 = is_free ? (uint32_t)~(uint64_t)q : (big ? 0u : sg);
-    const uint32_t w1 = ceil_log2_u32(sg) + w.shift;
-    const uint64_t mfree = ballot(is_free);
-    const uint32_t n = (uint32_t)min<int64_t>(64, b1 - base);
-    uint32_t olo = 0, ohi = 0;
-    for (uint32_t j = 0; j < n; ++j) {
-      const uint32_t v0 = rdlane(w0, j);
-      int64_t r;
-      if ((mfree >> j) & 1ull) {
-        r = w.free_draw(v0);
-      } else if (v0 == 0u) {
-        r = kFail;
-      } else {
-        r = w.alloc(v0, ALGO == kSegFit ? rdlane(w1, j) : 0u);
-      }
-      if (r == kOverflow) return false;
+      if (r == kOverflow) { done = j; break; }
       if (r == kENoMeta && st == 0) st = (int32_t)kENoMeta;
       olo = put_lane(olo, j, (uint32_t)(uint64_t)r);
       ohi = put_lane(ohi, j, (uint32_t)((uint64_t)r >> 32));
     }
-    if (base + lane < b1) p.res[base + lane] = (int64_t)(((uint64_t)ohi << 32) | olo);
+    if (lane < done) p.res[base + lane] = (int64_t)(((uint64_t)ohi << 32) | olo);
+    if (done < n) return base + done;
   }
+  return to;
+}
+
+// Canonical state and status of a finished heap.
+template <typename Core>
+__device__ __forceinline__ void finish_heap(const ReplayParams& p, Core& w, int64_t heap,
+                                            int32_t st) {
   if (p.state) {
     const int64_t so = p.state_off[heap], cap = p.state_off[heap + 1] - so;
     const int64_t need = w.dump(p.state + so, cap);
-    if (lane == 0) p.state_len[heap] = need;
+    if (lane_id() == 0) p.state_len[heap] = need;
     if (need > cap && st == 0) st = (int32_t)kERange;
   }
-  if (lane == 0) p.status[heap] = st;
-  return true;
+  if (lane_id() == 0) p.status[heap] = st;
+}
+
+template <int ALGO, int RF, int RL>
+__device__ void replay_heap(const ReplayParams& p, const Cold& c, const HeapRegs& regs,
+                            int64_t heap) {
+  WaveHeap<ALGO, RF, RL> w(c, regs, p.cap_free, p.cap_live);
+  w.init();
+  int32_t st = 0;
+  run_requests<ALGO>(p, w, p.req_off[heap], p.req_off[heap + 1], w.h.shift, w.h.arena, st);
+  finish_heap(p, w, heap, st);
+}
+
+// Lean path (hda_lean.h).  A heap whose tables outgrow the lean tiers moves
+// them into the general core's layout -- the same LDS bytes, then the wave's
+// device-memory spill slot -- and continues there from the request that
+// did not fit.
+template <int ALGO, int RF>
+__device__ void lean_replay_heap(const ReplayParams& p, const LeanLds& lds, const Cold& c,
+                                 const HeapRegs& regs, int64_t heap) {
+  LeanHeap<ALGO, RF> w(lds, regs, p.cap_free, p.cap_live);
+  w.init();
+  int32_t st = 0;
+  const int64_t b1 = p.req_off[heap + 1];
+  const int64_t pos = run_requests<ALGO>(p, w, p.req_off[heap], b1, w.shift, w.arena, st);
+  if (pos == b1) {
+    finish_heap(p, w, heap, st);
+    return;
+  }
+  WaveHeap<ALGO, 0, 0> g(c, regs, p.cap_free, p.cap_live);
+  w.migrate(c, g.h);
+  if (lane_id() == 0 && p.migrated) atomicAdd(p.migrated, 1u);
+  run_requests<ALGO>(p, g, pos, b1, g.h.shift, g.h.arena, st);
+  finish_heap(p, g, heap, st);
 }
 
 // Heap with invalid parameters: every result and the status are E_INVAL.
@@ -188,19 +173,16 @@ __device__ __forceinline__ void replay_one_heap(const ReplayParams& p, const Col
   replay_heap<ALGO, RF, RL>(p, c, h, heap);
 }
 
-// Lean replay of one heap known to use algorithm ALGO; a heap that outgrows
-// the fast tiers is appended to the overflow list.
+// Lean replay of one heap known to use algorithm ALGO.
 template <int ALGO, int RF>
 __device__ __forceinline__ void lean_one_heap(const ReplayParams& p, const LeanLds& lds,
-                                              int64_t heap) {
+                                              const Cold& c, int64_t heap) {
   HeapRegs h;
   if (!heap_params(p, heap, h) || h.algo != ALGO) {
     reject_heap(p, heap);
     return;
   }
-  if (!lean_replay_heap<ALGO, RF>(p, lds, h, heap)) {
-    if (lane_id() == 0) p.ovf_list[atomicAdd(p.ovf_count, 1u)] = (int32_t)heap;
-  }
+  lean_replay_heap<ALGO, RF>(p, lds, c, h, heap);
 }
 
 // Any algorithm (used where one program must serve every heap).

@@ -31,12 +31,12 @@ struct LaneJob {
 LaneJob g_job;
 
 template <int RF>
-void lean_any(const ReplayParams& p, const LeanLds& lds, int64_t heap) {
+void lean_any(const ReplayParams& p, const LeanLds& lds, const Cold& c, int64_t heap) {
   switch (p.algo[heap]) {
-    case kFirstFit: lean_one_heap<kFirstFit, RF>(p, lds, heap); break;
-    case kNextFit: lean_one_heap<kNextFit, RF>(p, lds, heap); break;
-    case kBestFit: lean_one_heap<kBestFit, RF>(p, lds, heap); break;
-    default: lean_one_heap<kSegFit, RF>(p, lds, heap); break;
+    case kFirstFit: lean_one_heap<kFirstFit, RF>(p, lds, c, heap); break;
+    case kNextFit: lean_one_heap<kNextFit, RF>(p, lds, c, heap); break;
+    case kBestFit: lean_one_heap<kBestFit, RF>(p, lds, c, heap); break;
+    default: lean_one_heap<kSegFit, RF>(p, lds, c, heap); break;
   }
 }
 
@@ -45,8 +45,8 @@ void lane_main() {
     case 0: replay_any_heap<0, 0>(*g_job.p, *g_job.c, g_job.heap); break;
     case 1: replay_any_heap<1, 2>(*g_job.p, *g_job.c, g_job.heap); break;
     case 2: replay_any_heap<4, 8>(*g_job.p, *g_job.c, g_job.heap); break;
-    case 3: lean_any<1>(*g_job.p, *g_job.lds, g_job.heap); break;
-    default: lean_any<4>(*g_job.p, *g_job.lds, g_job.heap); break;
+    case 3: lean_any<1>(*g_job.p, *g_job.lds, *g_job.c, g_job.heap); break;
+    default: lean_any<4>(*g_job.p, *g_job.lds, *g_job.c, g_job.heap); break;
   }
   // a finished lane keeps handing over until every lane has finished
   g_job.done++;
@@ -80,8 +80,8 @@ void run_wave(EmuWave& w, std::vector<std::vector<uint8_t>>& stacks) {
 
 // shape: general core with 0 = no register part, 1 = (1, 2) chunks, 2 = (4, 8)
 // chunks in registers; lean core with 3 = one, 4 = four free chunks in
-// registers, where a heap that outgrows its tiers is replayed again by the
-// general core with no register part (overflowed[h] = 1).  kf/kl: entries in
+// registers, where a heap that outgrows its tiers moves to the general core
+// on the same "LDS" plus spill tables (overflowed[h] = 1).  kf/kl: entries in
 // "LDS"; cap_free/cap_live: capacities.
 extern "C" int emu_replay(int64_t H, const int64_t* arena, const int64_t* align,
                           const int32_t* algo, const int64_t* req_off, const int64_t* req,
@@ -95,10 +95,6 @@ extern "C" int emu_replay(int64_t H, const int64_t* arena, const int64_t* align,
   p.res = res; p.state = state; p.state_off = state_off; p.state_len = state_len;
   p.status = status;
   const bool lean = shape >= 3;
-  const uint32_t lean_rf = shape == 3 ? 1u : 4u;
-  // lean tiers: LDS entries beyond the register chunks
-  const uint32_t lkf = kf, lkl = kl;
-  if (lean) { kf = 64; kl = 128; shape = 0; }  // general tiers of the second pass
   const uint32_t hf = 64u * kShapeRF[shape], hl = 64u * kShapeRL[shape];
   const uint32_t coldF = cap_free > hf ? cap_free - hf : 0u;
   const uint32_t coldL = cap_live > hl ? cap_live - hl : 0u;
@@ -107,11 +103,8 @@ extern "C" int emu_replay(int64_t H, const int64_t* arena, const int64_t* align,
   p.cap_free = cap_free; p.cap_live = cap_live;
   p.kf = kf; p.kl = kl; p.sf = coldF - kf; p.sl = coldL - kl;
   std::vector<uint8_t> lds(size_t(kf) * 12 + size_t(kl) * 8 + 16);
-  std::vector<uint8_t> llds(size_t(lkf) * 12 + size_t(lkl) * 8 + 16);
-  std::vector<int32_t> ovf_list(H + 1);
-  uint32_t ovf_count = 0;
-  p.ovf_list = ovf_list.data();
-  p.ovf_count = &ovf_count;
+  uint32_t migrated = 0;
+  p.migrated = &migrated;
   std::vector<Ent> gf(p.sf + 64), gl(p.sl + 64);
   std::vector<uint32_t> gst(p.sf + 64);
   const size_t stack_bytes = 256 * 1024;
@@ -131,23 +124,17 @@ extern "C" int emu_replay(int64_t H, const int64_t* arena, const int64_t* align,
     c.kf = kf; c.kl = kl; c.cf = coldF; c.cl = coldL;
     uint64_t n_sync = 0;
     if (lean) {
-      std::memset(llds.data(), 0xA5, llds.size());
       LeanLds ll;
-      ll.cf = reinterpret_cast<Ent*>(llds.data());
-      ll.ck = reinterpret_cast<uint32_t*>(llds.data() + size_t(lkf) * 8);
-      ll.lv = reinterpret_cast<Ent*>(llds.data() + size_t(lkf) * 12);
-      ll.kf = lkf;
-      ll.kl = lkl;
-      const uint32_t before = ovf_count;
-      g_job = LaneJob{&p, &c, &ll, h, lean_rf == 1 ? 3 : 4, 0};
+      ll.cf = c.lf;
+      ll.ck = c.lst;
+      ll.lv = c.ll;
+      ll.kf = kf;
+      ll.kl = kl;
+      const uint32_t before = migrated;
+      g_job = LaneJob{&p, &c, &ll, h, shape, 0};
       run_wave(w, stacks);
-      n_sync += w.syncs;
-      if (overflowed) overflowed[h] = ovf_count != before;
-      if (ovf_count != before) {  // second pass on the general core
-        g_job = LaneJob{&p, &c, nullptr, h, 0, 0};
-        run_wave(w, stacks);
-        n_sync += w.syncs;
-      }
+      n_sync = w.syncs;
+      if (overflowed) overflowed[h] = migrated != before;
     } else {
       g_job = LaneJob{&p, &c, nullptr, h, shape, 0};
       run_wave(w, stacks);

@@ -94,7 +94,8 @@ def test_invalid_heap_parameters():
     check(b, res, states, status, heaps=[0, 2])
 
 
-# ---- lean core (registers + LDS, second pass on the general core) ----
+# ---- lean core (registers + LDS; a heap that outgrows them moves to the
+# general core and continues there) ----
 
 @pytest.mark.parametrize("algo", ALGOS)
 def test_lean_single_heap_64KiB(algo):
@@ -118,9 +119,10 @@ def test_lean_16MiB_heap_cold_entries_in_lds(algo):
 
 
 @pytest.mark.parametrize("algo", ALGOS)
-def test_lean_overflow_replays_on_general_core(algo):
-    """Tiers far smaller than the tables: the heap stops on the lean core and
-    is replayed from the start on the general core, with the same results."""
+def test_lean_overflow_moves_to_general_core(algo):
+    """Tiers far smaller than the tables: the heap's tables move into the
+    general core's layout mid-trace and the replay continues there, with the
+    same results."""
     b = W.uniform_batch(heaps=1, n=2000, algo=algo)
     ovf = np.zeros(b.heaps, np.uint8)
     res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=4096, cl=4096, shape=3,
@@ -131,7 +133,7 @@ def test_lean_overflow_replays_on_general_core(algo):
 
 def test_lean_capacity_within_tiers_is_exact():
     """Capacities no larger than the tiers: E_NOMETA on the lean core itself,
-    no second pass, results equal to the general core's."""
+    no move to the general core, results equal to the general core's."""
     b = W.uniform_batch(heaps=1, n=1500, algo=2)
     ovf = np.zeros(b.heaps, np.uint8)
     res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=64, cl=64, shape=3,

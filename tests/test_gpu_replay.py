@@ -93,7 +93,7 @@ SPILL_TUNINGS = {
     "general_no_lds": hda.tuning(heaps_per_group=4, reg_free=-1, reg_live=-1, lds_free=-1,
                                  lds_live=-1),
     # lean core with tiers too small for these heaps: every heap outgrows
-    # them and is replayed again on the general core
+    # them and moves to the general core mid-trace
     "lean_overflow": hda.tuning(heaps_per_group=2, reg_free=4, lds_free=-1, lds_live=64),
     "lean_lds_overflow": hda.tuning(heaps_per_group=4, reg_free=4, reg_live=-1, lds_free=64,
                                     lds_live=128),
