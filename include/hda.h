@@ -142,6 +142,34 @@ int hda_replay(const hda_batch_desc *d, void *stream);
  * (H launches of one wavefront each, in `order`, on `stream`). */
 int hda_replay_per_heap(const hda_batch_desc *d, void *stream);
 
+/* Autotuner.  Picks heaps_per_group and the LDS residency (lds_free,
+ * lds_live) of the default path for `d` by timing candidate tunings, with HIP
+ * events on `stream`, on the batch's longest heaps (which set the makespan):
+ * up to sample_heaps of them (0 = as many as the device holds at once,
+ * capped at 64 M requests in total), full traces.  The fastest candidate is
+ * written to *out; put it into d->tuning (and size the workspace for it)
+ * before the real replay.  The sampled heaps' results, states and status are
+ * overwritten by the trial replays, so the real replay must follow.
+ * Temporary device memory (the sample order and the trials' workspace) is
+ * allocated and freed here.  Synchronous.  HDA_E_INVAL for an invalid
+ * descriptor, HDA_E_DEVICE on a HIP failure. */
+int hda_replay_autotune(const hda_batch_desc *d, int32_t sample_heaps, void *stream,
+                        hda_tuning *out);
+
+/* One hda_replay call on `d` recorded as a hipGraph (the classify kernel, the
+ * per-algorithm launches and their fork/join over the library's streams),
+ * for callers that replay the same descriptor buffers repeatedly: each
+ * hda_graph_launch re-runs the whole replay from the heaps' initial state on
+ * `stream`, exactly as hda_replay would.  The descriptor's buffers must stay
+ * valid and in place while the graph exists; the graph records no memset.
+ * Library-owned; release with hda_graph_destroy.  Capture is synchronous.
+ * HDA_E_INVAL / HDA_E_RANGE as for hda_replay, HDA_E_DEVICE on a HIP
+ * failure. */
+typedef struct hda_graph hda_graph; /* opaque, library-owned */
+int hda_replay_capture(const hda_batch_desc *d, hda_graph **out);
+int hda_graph_launch(hda_graph *g, void *stream);
+int hda_graph_destroy(hda_graph *g);
+
 /* ------------------------------------------------------------------------ */
 /* Single heaps driven call by call (Alg. 6 init; Alg. 1-5 per call).       */
 /* ------------------------------------------------------------------------ */

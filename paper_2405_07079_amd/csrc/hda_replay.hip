@@ -15,6 +15,7 @@
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <numeric>
 #include <vector>
 
 #include "hda.h"
@@ -387,6 +388,24 @@ int classify(const hda_batch_desc* d, const Plan& pl, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? HDA_OK : HDA_E_DEVICE;
 }
 
+// Classify, then the per-algorithm launches on the library's side streams,
+// forked from and joined back to s.  The caller holds dc->enqueue.
+int enqueue(const hda_batch_desc* d, const Plan& pl, DeviceCtx* dc, hipStream_t s) {
+  int rc = classify(d, pl, s);
+  if (rc != HDA_OK) return rc;
+  if (hipEventRecord(dc->fork, s) != hipSuccess) return HDA_E_DEVICE;
+  for (int a = 0; a < 4; ++a) {
+    ReplayParams p = replay_params(d, pl, a);
+    if (hipStreamWaitEvent(dc->side[a], dc->fork, 0) != hipSuccess ||
+        launch(pl.set->fn[a], dim3((uint32_t)pl.main.groups[a]), dim3(64 * pl.main.W),
+               pl.main.lds_group, dc->side[a], p) != hipSuccess ||
+        hipEventRecord(dc->join[a], dc->side[a]) != hipSuccess ||
+        hipStreamWaitEvent(s, dc->join[a], 0) != hipSuccess)
+      return HDA_E_DEVICE;
+  }
+  return hipGetLastError() == hipSuccess ? HDA_OK : HDA_E_DEVICE;
+}
+
 }  // namespace
 
 extern "C" {
@@ -418,19 +437,7 @@ int hda_replay(const hda_batch_desc* d, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (!dc || !set_lds_attrs(pl)) return HDA_E_DEVICE;
   std::lock_guard<std::mutex> g(dc->enqueue);
-  int rc = classify(d, pl, s);
-  if (rc != HDA_OK) return rc;
-  if (hipEventRecord(dc->fork, s) != hipSuccess) return HDA_E_DEVICE;
-  for (int a = 0; a < 4; ++a) {
-    ReplayParams p = replay_params(d, pl, a);
-    if (hipStreamWaitEvent(dc->side[a], dc->fork, 0) != hipSuccess ||
-        launch(pl.set->fn[a], dim3((uint32_t)pl.main.groups[a]), dim3(64 * pl.main.W),
-               pl.main.lds_group, dc->side[a], p) != hipSuccess ||
-        hipEventRecord(dc->join[a], dc->side[a]) != hipSuccess ||
-        hipStreamWaitEvent(s, dc->join[a], 0) != hipSuccess)
-      return HDA_E_DEVICE;
-  }
-  return hipGetLastError() == hipSuccess ? HDA_OK : HDA_E_DEVICE;
+  return enqueue(d, pl, dc, s);
 }
 
 int hda_replay_per_heap(const hda_batch_desc* d, void* stream) {
@@ -460,6 +467,166 @@ int hda_replay_per_heap(const hda_batch_desc* d, void* stream) {
     }
   }
   return hipGetLastError() == hipSuccess ? HDA_OK : HDA_E_DEVICE;
+}
+
+// The longest heaps (by trace length) of `d`, longest first: at most
+// `want` of them and, past `min_heaps`, no more than `budget` requests.
+static std::vector<int32_t> longest_heaps(const std::vector<int64_t>& off, int64_t want,
+                                          int64_t min_heaps, int64_t budget) {
+  const int64_t H = (int64_t)off.size() - 1;
+  std::vector<int32_t> idx(H);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) {
+    return off[a + 1] - off[a] > off[b + 1] - off[b];
+  });
+  std::vector<int32_t> out;
+  int64_t total = 0;
+  for (int64_t k = 0; k < H && k < want; ++k) {
+    const int64_t len = off[idx[k] + 1] - off[idx[k]];
+    if (k >= min_heaps && total + len > budget) break;
+    total += len;
+    out.push_back(idx[k]);
+  }
+  return out;
+}
+
+int hda_replay_autotune(const hda_batch_desc* d, int32_t sample_heaps, void* stream,
+                        hda_tuning* out) {
+  Plan pl;
+  if (!out || !desc_ok(d) || sample_heaps < 0 || !make_plan(d, true, &pl)) return HDA_E_INVAL;
+  DeviceCtx* dc = device_ctx();
+  if (!dc) return HDA_E_DEVICE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (d->n_heaps == 0) return hda_replay_resolve(d, out);
+  // trace lengths on the host
+  std::vector<int64_t> off(d->n_heaps + 1);
+  if (hipMemcpyAsync(off.data(), d->req_off, off.size() * 8, hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return HDA_E_DEVICE;
+  // default sample: the heaps the device holds at once under the default tuning
+  const int64_t resident = pl.main.slots[0];
+  const int64_t want = sample_heaps > 0 ? sample_heaps : resident;
+  const std::vector<int32_t> sample = longest_heaps(off, want, dc->cus, int64_t(64) << 20);
+  // candidates: heaps per workgroup x LDS residency of the lean path
+  std::vector<hda_tuning> cand;
+  const uint32_t lds_pairs[][2] = {{64, 512}, {128, 1024}, {256, 2048}, {512, 4096}};
+  for (int32_t W : {2, 4, 8})
+    for (const auto& kv : lds_pairs) {
+      hda_tuning t = d->tuning;
+      t.heaps_per_group = W;
+      t.reg_free = t.reg_free < 0 ? 0 : t.reg_free;
+      t.reg_live = 0;
+      t.lds_free = (int32_t)kv[0];
+      t.lds_live = (int32_t)kv[1];
+      t.groups = 0;
+      cand.push_back(t);
+    }
+  hda_batch_desc dd = *d;
+  dd.n_heaps = (int64_t)sample.size();
+  size_t ws = 0;
+  std::vector<hda_tuning> ok;
+  for (const hda_tuning& t : cand) {
+    dd.tuning = t;
+    Plan p2;
+    if (make_plan(&dd, true, &p2)) {
+      ok.push_back(t);
+      ws = std::max(ws, p2.bytes);
+    }
+  }
+  if (ok.empty()) return hda_replay_resolve(d, out);
+  int32_t* order = nullptr;
+  void* work = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = HDA_E_DEVICE;
+  float best = -1.0f;
+  hda_tuning pick = ok[0];
+  if (hipMalloc(&order, sample.size() * 4) == hipSuccess && hipMalloc(&work, ws) == hipSuccess &&
+      hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+      hipMemcpyAsync(order, sample.data(), sample.size() * 4, hipMemcpyHostToDevice, s) ==
+          hipSuccess) {
+    dd.order = order;
+    dd.workspace = work;
+    dd.workspace_bytes = ws;
+    rc = HDA_OK;
+    // one untimed trial first (code objects, LDS attributes), then one each
+    for (size_t i = 0; i <= ok.size() && rc == HDA_OK; ++i) {
+      dd.tuning = ok[i == 0 ? 0 : i - 1];
+      if (hipEventRecord(e0, s) != hipSuccess || hda_replay(&dd, s) != HDA_OK ||
+          hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        rc = HDA_E_DEVICE;
+        break;
+      }
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = HDA_E_DEVICE;
+      if (i > 0 && (best < 0.0f || ms < best)) {
+        best = ms;
+        pick = ok[i - 1];
+      }
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (order) (void)hipFree(order);
+  if (work) (void)hipFree(work);
+  if (rc != HDA_OK) return rc;
+  hda_batch_desc dp = *d;
+  dp.tuning = pick;
+  return hda_replay_resolve(&dp, out);
+}
+
+}  // extern "C"
+
+struct hda_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+int hda_replay_capture(const hda_batch_desc* d, hda_graph** out) {
+  Plan pl;
+  if (!out || !desc_ok(d) || !make_plan(d, true, &pl) || d->n_heaps == 0) return HDA_E_INVAL;
+  if (!d->workspace || d->workspace_bytes < pl.bytes) return HDA_E_RANGE;
+  DeviceCtx* dc = device_ctx();
+  if (!dc || !set_lds_attrs(pl)) return HDA_E_DEVICE;
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return HDA_E_DEVICE;
+  hda_graph* g = new hda_graph;
+  int rc = HDA_E_DEVICE;
+  {
+    std::lock_guard<std::mutex> lk(dc->enqueue);
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      const int erc = enqueue(d, pl, dc, cs);
+      const hipError_t ec = hipStreamEndCapture(cs, &g->graph);
+      if (erc == HDA_OK && ec == hipSuccess &&
+          hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) == hipSuccess)
+        rc = HDA_OK;
+      else if (erc != HDA_OK)
+        rc = erc;
+    }
+  }
+  (void)hipStreamDestroy(cs);
+  if (rc != HDA_OK) {
+    hda_graph_destroy(g);
+    return rc;
+  }
+  *out = g;
+  return HDA_OK;
+}
+
+int hda_graph_launch(hda_graph* g, void* stream) {
+  if (!g || !g->exec) return HDA_E_INVAL;
+  return hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? HDA_OK
+                                                                               : HDA_E_DEVICE;
+}
+
+int hda_graph_destroy(hda_graph* g) {
+  if (!g) return HDA_E_INVAL;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return HDA_OK;
 }
 
 }  // extern "C"

@@ -95,7 +95,8 @@ HDA_OP_ALLOC, HDA_OP_FREE = 1, 2
 _lib = None
 
 EXPORTS = ["hda_replay_workspace", "hda_replay_resolve", "hda_replay",
-           "hda_replay_per_heap", "hda_heap_create", "hda_heap_destroy", "hda_alloc",
+           "hda_replay_per_heap", "hda_replay_autotune", "hda_replay_capture",
+           "hda_graph_launch", "hda_graph_destroy", "hda_heap_create", "hda_heap_destroy", "hda_alloc",
            "hda_free", "hda_heap_state", "hda_set_meta_budget", "hda_strerror",
            "hda_serve_start", "hda_serve_open", "hda_serve_submit", "hda_serve_poll",
            "hda_serve_wait", "hda_serve_close", "hda_serve_stop", "hda_serve_load"]
@@ -119,6 +120,14 @@ def lib():
         L.hda_replay.argtypes = [D, vp]
         L.hda_replay_per_heap.restype = ctypes.c_int
         L.hda_replay_per_heap.argtypes = [D, vp]
+        L.hda_replay_autotune.restype = ctypes.c_int
+        L.hda_replay_autotune.argtypes = [D, ctypes.c_int32, vp, ctypes.POINTER(hda_tuning)]
+        L.hda_replay_capture.restype = ctypes.c_int
+        L.hda_replay_capture.argtypes = [D, ctypes.POINTER(vp)]
+        L.hda_graph_launch.restype = ctypes.c_int
+        L.hda_graph_launch.argtypes = [vp, vp]
+        L.hda_graph_destroy.restype = ctypes.c_int
+        L.hda_graph_destroy.argtypes = [vp]
         L.hda_heap_create.restype = ctypes.c_int
         L.hda_heap_create.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int,
                                       ctypes.c_uint32, ctypes.POINTER(vp)]
@@ -287,6 +296,51 @@ def hda_replay_per_heap(db: DeviceBatch, stream=None) -> None:
     """Enqueue one launch per heap (the per-heap baseline) on `stream`."""
     _check(lib().hda_replay_per_heap(ctypes.byref(db.desc()), _stream_ptr(stream)),
            "hda_replay_per_heap")
+
+
+def hda_replay_autotune(db: DeviceBatch, sample_heaps: int = 0, stream=None) -> tuple:
+    """Time candidate tunings on the batch's longest heaps; returns the
+    fastest as a tuning tuple (the sampled heaps' outputs are overwritten)."""
+    out = hda_tuning()
+    _check(lib().hda_replay_autotune(ctypes.byref(db.desc()), int(sample_heaps),
+                                     _stream_ptr(stream), ctypes.byref(out)),
+           "hda_replay_autotune")
+    return tuple(getattr(out, f) for f in TUNING_FIELDS)
+
+
+def retune(db: DeviceBatch, tuning) -> DeviceBatch:
+    """Set a batch's tuning and give it a workspace large enough for it."""
+    import torch
+    db.tuning = tuple(tuning)
+    ws = hda_replay_workspace(db)
+    if db.workspace is None or db.workspace.numel() < ws:
+        db.workspace = torch.empty(max(ws, 256), dtype=torch.uint8, device=db.res.device)
+    return db
+
+
+class ReplayGraph:
+    """One hda_replay call on a DeviceBatch recorded as a hipGraph."""
+
+    def __init__(self, db: DeviceBatch):
+        self._db = db            # the graph points into its buffers
+        h = ctypes.c_void_p()
+        _check(lib().hda_replay_capture(ctypes.byref(db.desc()), ctypes.byref(h)),
+               "hda_replay_capture")
+        self._g = h
+
+    def launch(self, stream=None) -> None:
+        _check(lib().hda_graph_launch(self._g, _stream_ptr(stream)), "hda_graph_launch")
+
+    def close(self) -> None:
+        if self._g:
+            _check(lib().hda_graph_destroy(self._g), "hda_graph_destroy")
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def states_to_host(db: DeviceBatch, heaps=None):

@@ -230,3 +230,46 @@ def test_empty_batch_and_empty_heaps():
     db.n_heaps = 0
     hda.hda_replay(db)
     torch.cuda.synchronize()
+
+
+def test_graph_replays_match_eager():
+    """A captured replay, launched several times with eager work between the
+    launches, rewrites every output each time exactly as the eager call."""
+    b = W.concat([c2_like(8, 6000, a) for a in ALGOS], "mixed")
+    say("case: hipGraph of one replay call, 3 launches")
+    ref_res, ref_states, ref_status = gpu_replay(b)
+    db = hda.upload(b)
+    g = hda.ReplayGraph(db)
+    other = hda.upload(c2_like(4, 3000, 3))
+    try:
+        for k in range(3):
+            db.res.fill_(0x5a5a)
+            db.status.fill_(77)
+            db.state.fill_(-9)
+            g.launch()
+            torch.cuda.synchronize()
+            assert np.array_equal(db.res.cpu().numpy()[:b.requests], ref_res), f"launch {k}"
+            assert np.array_equal(db.status.cpu().numpy(), ref_status)
+            got = hda.states_to_host(db)
+            assert all(np.array_equal(x, y) for x, y in zip(got, ref_states))
+            hda.hda_replay(other)            # eager work between launches
+            torch.cuda.synchronize()
+    finally:
+        g.close()
+
+
+def test_autotune_picks_a_valid_tuning():
+    b = W.uneven_batch(heaps=512, len_scale=0.01)
+    say(f"case: autotune on an uneven batch, {b.requests} requests")
+    db = hda.upload(b)
+    tu = hda.hda_replay_autotune(db)
+    assert tu[1] == 4 and tu[3] > 0 and tu[4] > 0       # lean path, LDS tiers
+    hda.retune(db, tu)
+    hda.hda_replay(db)
+    torch.cuda.synchronize()
+    res = db.res.cpu().numpy()[:b.requests]
+    rng = np.random.default_rng(1)
+    lens = np.diff(b.req_off)
+    heaps = sorted(set(rng.choice(b.heaps, 60, replace=False).tolist())
+                   | set(np.argsort(-lens)[:6].tolist()))
+    check_against_oracle(b, res, hda.states_to_host(db), db.status.cpu().numpy(), heaps)
