@@ -53,16 +53,18 @@ constexpr int64_t kFail = -1, kEInval = -2, kEBadFree = -3, kENoMeta = -4,
 enum : int { kFirstFit = 0, kNextFit = 1, kBestFit = 2, kSegFit = 3 };
 
 // Wave-wide minimum of a u32; every lane must be active.  Row-local
-// Hillis-Steele steps with DPP row shifts (identity shifted in), then the four
-// row minima are combined on the scalar unit.
+// Hillis-Steele steps with DPP row shifts (identity shifted in) leave each
+// row's minimum in its lane 15; two row broadcasts fold the four rows into
+// lane 63.
 __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
   const uint32_t I = 0xffffffffu;  // identity of unsigned min
   v = min(v, row_shr<1>(I, v));
   v = min(v, row_shr<2>(I, v));
   v = min(v, row_shr<4>(I, v));
   v = min(v, row_shr<8>(I, v));
-  const uint32_t r0 = rdlane(v, 15), r1 = rdlane(v, 31), r2 = rdlane(v, 47), r3 = rdlane(v, 63);
-  return min(min(r0, r1), min(r2, r3));
+  v = min(v, row_bcast15(I, v));
+  v = min(v, row_bcast31(I, v));
+  return rdlane(v, 63);
 }
 
 __device__ __forceinline__ uint32_t floor_log2_u32(uint32_t x) {  // x >= 1

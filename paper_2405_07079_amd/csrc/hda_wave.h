@@ -49,6 +49,18 @@ __device__ __forceinline__ uint32_t row_shr(uint32_t old, uint32_t src) {
   return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x110 + K, 0xf, 0xf, false);
 }
 
+// Rows 1 and 3 receive lane 15 of the row below (lanes 15 and 47); rows 0
+// and 2 keep `old` (DPP row_bcast:15 under row mask 0b1010).
+__device__ __forceinline__ uint32_t row_bcast15(uint32_t old, uint32_t src) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x142, 0xa, 0xf, false);
+}
+
+// Rows 2 and 3 receive lane 31; rows 0 and 1 keep `old` (DPP row_bcast:31
+// under row mask 0b1100).
+__device__ __forceinline__ uint32_t row_bcast31(uint32_t old, uint32_t src) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x143, 0xc, 0xf, false);
+}
+
 __device__ __forceinline__ uint32_t shfl(uint32_t v, uint32_t src_lane) {
   return (uint32_t)__shfl((int)v, (int)src_lane);
 }

@@ -80,6 +80,24 @@ inline uint32_t row_shr(uint32_t old, uint32_t src) {
   });
 }
 
+// Rows 1 and 3 receive lane 15 of the row below (lanes 15 and 47); rows 0
+// and 2 keep `old`.
+inline uint32_t row_bcast15(uint32_t old, uint32_t src) {
+  const uint32_t me = emu_lane;
+  return exchange(src, [me, old](const uint64_t* x) {
+    const uint32_t row = me >> 4;
+    return (row & 1u) ? (uint32_t)x[16u * row - 1u] : old;
+  });
+}
+
+// Rows 2 and 3 receive lane 31; rows 0 and 1 keep `old`.
+inline uint32_t row_bcast31(uint32_t old, uint32_t src) {
+  const uint32_t me = emu_lane;
+  return exchange(src, [me, old](const uint64_t* x) {
+    return (me >> 4) >= 2u ? (uint32_t)x[31] : old;
+  });
+}
+
 inline uint32_t shfl(uint32_t v, uint32_t src_lane) {
   return exchange(v, [src_lane](const uint64_t* x) { return (uint32_t)x[src_lane & 63u]; });
 }
