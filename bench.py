@@ -67,6 +67,25 @@ def recorded_traffic(algo_names):
     return float(np.mean([t[a] for a in algo_names]))
 
 
+def recorded_lds_conflicts():
+    """LDS bank-conflict cycles per request from the committed instruction-mix
+    summary, while the kernel sources match; else None."""
+    path = os.path.join(ROOT, "profiles", "replay_c2_instruction_mix.txt")
+    try:
+        with open(path) as f:
+            text = f.read()
+    except OSError:
+        return None
+    if kernel_source_hash() not in text:
+        return None
+    vals = []
+    for line in text.splitlines():
+        parts = line.split()
+        if len(parts) == 8 and parts[0] in ("best_fit", "seg_fit"):
+            vals.append(float(parts[7]))
+    return float(np.mean(vals)) if vals else None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -228,13 +247,20 @@ def main():
         for algo in algos:
             oracle.replay_batch(csub.with_algo(algo), threads=cores, want_state=True)
         ct = time.perf_counter() - t1
+        one = batch.subset(np.arange(min(16, C)))
+        t1 = time.perf_counter()
+        for algo in algos:
+            oracle.replay_batch(one.with_algo(algo), threads=1, want_state=True)
+        c1 = time.perf_counter() - t1
         cpu = {"value": csub.requests * len(algos) / ct, "unit": "ops/s", "cores": cores,
+               "value_1_thread": one.requests * len(algos) / c1,
                "kind": "oracle",
                "sample": f"first {C} heaps of the batch x (best fit, seg fit), "
                          f"{csub.requests * len(algos)} requests, {ct:.1f} s wall "
                          f"on {cores} threads"}
         log(f"[bench] cpu oracle: {cpu['value'] / 1e6:.2f} M ops/s on {cores} threads")
 
+    traffic = recorded_traffic([W.ALGO_NAMES[a] for a in algos])
     out = {
         "metric": METRIC,
         "value": value,
@@ -264,8 +290,13 @@ def main():
                             "batched_speedup": value / per_heap_value},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": recorded_traffic([W.ALGO_NAMES[a] for a in algos]),
+                     "traffic": traffic,
                      "traffic_unit": "bytes per launch",
+                     "traffic_frac": (None if traffic is None else
+                                      traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS),
+                     # free and live tables stay in VGPRs and LDS for this workload
+                     "metadata_hbm_bytes_per_request": 0,
+                     "lds_bank_conflict_cycles_per_request": recorded_lds_conflicts(),
                      "kernel": "replay_kernel",
                      "avg_launch_ms": avg_launch_s * 1e3,
                      "bytes_per_request": BYTES_PER_REQUEST,
