@@ -144,15 +144,16 @@ int hda_replay_per_heap(const hda_batch_desc *d, void *stream);
 
 /* Autotuner.  Picks heaps_per_group and the LDS residency (lds_free,
  * lds_live) of the default path for `d` by timing candidate tunings, with HIP
- * events on `stream`, on the batch's longest heaps (which set the makespan):
- * up to sample_heaps of them (0 = as many as the device holds at once,
- * capped at 64 M requests in total), full traces.  The fastest candidate is
- * written to *out; put it into d->tuning (and size the workspace for it)
- * before the real replay.  The sampled heaps' results, states and status are
- * overwritten by the trial replays, so the real replay must follow.
- * Temporary device memory (the sample order and the trials' workspace) is
- * allocated and freed here.  Synchronous.  HDA_E_INVAL for an invalid
- * descriptor, HDA_E_DEVICE on a HIP failure. */
+ * events on `stream`, on a private copy of the batch's longest heaps (which
+ * set the makespan): up to sample_heaps of them (0 = as many as the device
+ * holds at once), each trace cut to its first 65,536 requests, at most 16 M
+ * requests in all.  Candidates: 1, 2, 4, 8 or 16 heaps per workgroup x
+ * (lds_free, lds_live) = (64, 512), (128, 1024), (256, 2048), (512, 4096),
+ * those that fit the device's LDS.  The fastest is written to *out; put it
+ * into d->tuning (and size the workspace for it) before the replay.  The
+ * caller's buffers are only read.  Temporary device memory is allocated and
+ * freed here.  Synchronous.  HDA_E_INVAL for an invalid descriptor,
+ * HDA_E_DEVICE on a HIP failure. */
 int hda_replay_autotune(const hda_batch_desc *d, int32_t sample_heaps, void *stream,
                         hda_tuning *out);
 

@@ -469,10 +469,11 @@ int hda_replay_per_heap(const hda_batch_desc* d, void* stream) {
   return hipGetLastError() == hipSuccess ? HDA_OK : HDA_E_DEVICE;
 }
 
-// The longest heaps (by trace length) of `d`, longest first: at most
-// `want` of them and, past `min_heaps`, no more than `budget` requests.
+// The longest heaps (by trace length), longest first: at most `want` of them
+// and, past `min_heaps`, no more than `budget` requests once each trace is cut
+// to `cut` requests.
 static std::vector<int32_t> longest_heaps(const std::vector<int64_t>& off, int64_t want,
-                                          int64_t min_heaps, int64_t budget) {
+                                          int64_t min_heaps, int64_t budget, int64_t cut) {
   const int64_t H = (int64_t)off.size() - 1;
   std::vector<int32_t> idx(H);
   std::iota(idx.begin(), idx.end(), 0);
@@ -482,7 +483,7 @@ static std::vector<int32_t> longest_heaps(const std::vector<int64_t>& off, int64
   std::vector<int32_t> out;
   int64_t total = 0;
   for (int64_t k = 0; k < H && k < want; ++k) {
-    const int64_t len = off[idx[k] + 1] - off[idx[k]];
+    const int64_t len = std::min(off[idx[k] + 1] - off[idx[k]], cut);
     if (k >= min_heaps && total + len > budget) break;
     total += len;
     out.push_back(idx[k]);
@@ -492,26 +493,43 @@ static std::vector<int32_t> longest_heaps(const std::vector<int64_t>& off, int64
 
 int hda_replay_autotune(const hda_batch_desc* d, int32_t sample_heaps, void* stream,
                         hda_tuning* out) {
+  constexpr int64_t kCut = 65536, kBudget = int64_t(16) << 20;
   Plan pl;
   if (!out || !desc_ok(d) || sample_heaps < 0 || !make_plan(d, true, &pl)) return HDA_E_INVAL;
   DeviceCtx* dc = device_ctx();
   if (!dc) return HDA_E_DEVICE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (d->n_heaps == 0) return hda_replay_resolve(d, out);
-  // trace lengths on the host
-  std::vector<int64_t> off(d->n_heaps + 1);
+  const int64_t H = d->n_heaps;
+  if (H == 0) return hda_replay_resolve(d, out);
+  // heap parameters and trace lengths on the host
+  std::vector<int64_t> off(H + 1), arena(H), align(H);
+  std::vector<int32_t> algo(H);
   if (hipMemcpyAsync(off.data(), d->req_off, off.size() * 8, hipMemcpyDeviceToHost, s) !=
           hipSuccess ||
+      hipMemcpyAsync(arena.data(), d->arena, H * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(align.data(), d->align, H * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(algo.data(), d->algo, H * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return HDA_E_DEVICE;
-  // default sample: the heaps the device holds at once under the default tuning
-  const int64_t resident = pl.main.slots[0];
-  const int64_t want = sample_heaps > 0 ? sample_heaps : resident;
-  const std::vector<int32_t> sample = longest_heaps(off, want, dc->cus, int64_t(64) << 20);
+  // sample: the longest heaps, as many as the device holds at once under the
+  // default tuning, each trace cut to its first kCut requests
+  const int64_t want = sample_heaps > 0 ? sample_heaps : pl.main.slots[0];
+  const std::vector<int32_t> sample = longest_heaps(off, want, dc->cus, kBudget, kCut);
+  const int64_t S = (int64_t)sample.size();
+  std::vector<int64_t> s_off(S + 1, 0), s_arena(S), s_align(S);
+  std::vector<int32_t> s_algo(S);
+  for (int64_t k = 0; k < S; ++k) {
+    const int32_t h = sample[k];
+    s_off[k + 1] = s_off[k] + std::min(off[h + 1] - off[h], kCut);
+    s_arena[k] = arena[h];
+    s_align[k] = align[h];
+    s_algo[k] = algo[h];
+  }
+  const int64_t N = std::max<int64_t>(s_off[S], 1);
   // candidates: heaps per workgroup x LDS residency of the lean path
   std::vector<hda_tuning> cand;
   const uint32_t lds_pairs[][2] = {{64, 512}, {128, 1024}, {256, 2048}, {512, 4096}};
-  for (int32_t W : {2, 4, 8})
+  for (int32_t W : {1, 2, 4, 8, 16})
     for (const auto& kv : lds_pairs) {
       hda_tuning t = d->tuning;
       t.heaps_per_group = W;
@@ -522,8 +540,12 @@ int hda_replay_autotune(const hda_batch_desc* d, int32_t sample_heaps, void* str
       t.groups = 0;
       cand.push_back(t);
     }
-  hda_batch_desc dd = *d;
-  dd.n_heaps = (int64_t)sample.size();
+  // the trial batch: its own buffers, so the caller's outputs are untouched
+  hda_batch_desc dd;
+  std::memset(&dd, 0, sizeof(dd));
+  dd.n_heaps = S;
+  dd.meta_free = d->meta_free;
+  dd.meta_live = d->meta_live;
   size_t ws = 0;
   std::vector<hda_tuning> ok;
   for (const hda_tuning& t : cand) {
@@ -535,20 +557,42 @@ int hda_replay_autotune(const hda_batch_desc* d, int32_t sample_heaps, void* str
     }
   }
   if (ok.empty()) return hda_replay_resolve(d, out);
-  int32_t* order = nullptr;
-  void* work = nullptr;
+  auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t o_arena = 0, o_align = up(o_arena + S * 8), o_algo = up(o_align + S * 8),
+               o_off = up(o_algo + S * 4), o_req = up(o_off + (S + 1) * 8),
+               o_res = up(o_req + N * 8), o_status = up(o_res + N * 8),
+               o_work = up(o_status + S * 4), bytes = o_work + ws;
+  uint8_t* buf = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = HDA_E_DEVICE;
   float best = -1.0f;
   hda_tuning pick = ok[0];
-  if (hipMalloc(&order, sample.size() * 4) == hipSuccess && hipMalloc(&work, ws) == hipSuccess &&
-      hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
-      hipMemcpyAsync(order, sample.data(), sample.size() * 4, hipMemcpyHostToDevice, s) ==
+  if (hipMalloc(&buf, bytes) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
+      hipEventCreate(&e1) == hipSuccess &&
+      hipMemcpyAsync(buf + o_arena, s_arena.data(), S * 8, hipMemcpyHostToDevice, s) ==
+          hipSuccess &&
+      hipMemcpyAsync(buf + o_align, s_align.data(), S * 8, hipMemcpyHostToDevice, s) ==
+          hipSuccess &&
+      hipMemcpyAsync(buf + o_algo, s_algo.data(), S * 4, hipMemcpyHostToDevice, s) ==
+          hipSuccess &&
+      hipMemcpyAsync(buf + o_off, s_off.data(), (S + 1) * 8, hipMemcpyHostToDevice, s) ==
           hipSuccess) {
-    dd.order = order;
-    dd.workspace = work;
-    dd.workspace_bytes = ws;
     rc = HDA_OK;
+    for (int64_t k = 0; k < S && rc == HDA_OK; ++k) {
+      const size_t n = (size_t)(s_off[k + 1] - s_off[k]);
+      if (n && hipMemcpyAsync(buf + o_req + s_off[k] * 8, d->req + off[sample[k]], n * 8,
+                              hipMemcpyDeviceToDevice, s) != hipSuccess)
+        rc = HDA_E_DEVICE;
+    }
+    dd.arena = reinterpret_cast<const int64_t*>(buf + o_arena);
+    dd.align = reinterpret_cast<const int64_t*>(buf + o_align);
+    dd.algo = reinterpret_cast<const int32_t*>(buf + o_algo);
+    dd.req_off = reinterpret_cast<const int64_t*>(buf + o_off);
+    dd.req = reinterpret_cast<const int64_t*>(buf + o_req);
+    dd.res = reinterpret_cast<int64_t*>(buf + o_res);
+    dd.status = reinterpret_cast<int32_t*>(buf + o_status);
+    dd.workspace = buf + o_work;
+    dd.workspace_bytes = ws;
     // one untimed trial first (code objects, LDS attributes), then one each
     for (size_t i = 0; i <= ok.size() && rc == HDA_OK; ++i) {
       dd.tuning = ok[i == 0 ? 0 : i - 1];
@@ -567,8 +611,10 @@ int hda_replay_autotune(const hda_batch_desc* d, int32_t sample_heaps, void* str
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  if (order) (void)hipFree(order);
-  if (work) (void)hipFree(work);
+  if (buf) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(buf);
+  }
   if (rc != HDA_OK) return rc;
   hda_batch_desc dp = *d;
   dp.tuning = pick;

@@ -299,8 +299,8 @@ def hda_replay_per_heap(db: DeviceBatch, stream=None) -> None:
 
 
 def hda_replay_autotune(db: DeviceBatch, sample_heaps: int = 0, stream=None) -> tuple:
-    """Time candidate tunings on the batch's longest heaps; returns the
-    fastest as a tuning tuple (the sampled heaps' outputs are overwritten)."""
+    """Time candidate tunings on a copy of the batch's longest heaps (traces
+    cut to 65,536 requests); returns the fastest as a tuning tuple."""
     out = hda_tuning()
     _check(lib().hda_replay_autotune(ctypes.byref(db.desc()), int(sample_heaps),
                                      _stream_ptr(stream), ctypes.byref(out)),
