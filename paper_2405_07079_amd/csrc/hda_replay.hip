@@ -1,14 +1,11 @@
 // Batched replay of many independent heaps on gfx950.
 //
-// A small classify kernel splits the caller's heap order by algorithm (and
-// sets heaps with invalid parameters aside, rejecting them); then one
-// persistent kernel per algorithm -- compiled for that algorithm alone, so the
-// register allocation fits its own tables -- replays its heaps, one wavefront
-// per heap, pulling them from a device queue in the caller's order (longest
-// trace first is the useful order for uneven batches).  The per-algorithm
-// launches run concurrently on library streams forked from and joined back to
-// the caller's stream, so a mixed batch finishes when its slowest algorithm
-// group does.
+// A small classify kernel keeps the heaps with valid parameters in the
+// caller's order (rejecting the others); then one persistent kernel replays
+// them, one wavefront per heap, each wave pulling the next heap from a device
+// queue.  The kernel holds all four algorithms and switches per heap, so a
+// mixed batch is taken in one order (longest trace first is the useful order
+// for uneven batches) instead of one algorithm after another.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,11 +24,12 @@ using namespace hda;
 
 namespace {
 
-constexpr int kClasses = 5;  // four algorithms + invalid
-// Queue words in the workspace: one per algorithm, then the number of heaps
+constexpr int kClasses = 2;  // heaps with valid parameters, and the others
+constexpr int kValid = 0, kInvalid = 1;
+// Queue words in the workspace: the heap queue, then the number of heaps
 // moved from the lean to the general core.
-constexpr int kQueueWords = 5;
-constexpr int kMigrated = 4;
+constexpr int kQueueWords = 2;
+constexpr int kMigrated = 1;
 
 struct ClassifyParams {
   const int64_t* arena;
@@ -55,21 +53,21 @@ __device__ __forceinline__ bool params_valid(const ClassifyParams& q, int64_t he
            (A / g) >= (int64_t(1) << 32));
 }
 
-// One workgroup.  Wave 0 compacts `order` into per-class lists keeping the
-// order (ballot + popcount below the lane); then every wave rejects a share of
-// the invalid heaps.
+// One workgroup.  Wave 0 compacts `order` into the lists of valid and invalid
+// heaps keeping the order (ballot + popcount below the lane); then every wave
+// rejects a share of the invalid heaps.
 __global__ void __launch_bounds__(1024) classify_kernel(ClassifyParams q) {
   const uint32_t lane = lane_id();
   const uint32_t wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
   __shared__ uint32_t counts[kClasses];
   if (wave == 0) {
-    uint32_t cnt[kClasses] = {0, 0, 0, 0, 0};
+    uint32_t cnt[kClasses] = {0, 0};
     const uint64_t below = (1ull << lane) - 1ull;
     for (int64_t base = 0; base < q.n_heaps; base += 64) {
       const int64_t k = base + lane;
       const bool in = k < q.n_heaps;
       const int64_t heap = in ? (q.order ? (int64_t)q.order[k] : k) : 0;
-      const int cls = in ? (params_valid(q, heap) ? q.algo[heap] : 4) : kClasses;
+      const int cls = in ? (params_valid(q, heap) ? kValid : kInvalid) : kClasses;
 #pragma unroll
       for (int a = 0; a < kClasses; ++a) {
         const uint64_t m = ballot(cls == a);
@@ -88,9 +86,9 @@ __global__ void __launch_bounds__(1024) classify_kernel(ClassifyParams q) {
     if (lane < (uint32_t)kQueueWords) q.queues[lane] = 0u;
   }
   __syncthreads();
-  const uint32_t bad = counts[4];
+  const uint32_t bad = counts[kInvalid];
   for (uint32_t i = wave; i < bad; i += waves) {
-    const int64_t heap = q.lists[4 * q.n_heaps + i];
+    const int64_t heap = q.lists[kInvalid * q.n_heaps + i];
     const int64_t b0 = q.req_off[heap], b1 = q.req_off[heap + 1];
     for (int64_t base = b0; base < b1; base += 64)
       if (base + lane < b1) q.res[base + lane] = kEInval;
@@ -139,19 +137,21 @@ __device__ __forceinline__ Cold general_tiers(const ReplayParams& p, HDA_LDS uin
   return c;
 }
 
-// General-path kernel for one algorithm.
-template <int ALGO>
+// General path for every heap (tables in LDS, then device memory).
 __global__ void __launch_bounds__(1024) general_kernel(ReplayParams p) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   const uint32_t wave = uniform(threadIdx.x >> 6);  // the same in every lane of the wave
   HDA_LDS uint8_t* mine = (HDA_LDS uint8_t*)smem + (size_t)wave * p.lds_wave_bytes;
   const uint64_t slot = (uint64_t)blockIdx.x * p.waves_per_group + wave;
   const Cold c = general_tiers(p, mine, slot);
-  for_each_heap(p, slot, [&](int64_t heap) __attribute__((always_inline)) { replay_one_heap<ALGO, 0, 0>(p, c, heap); });
+  for_each_heap(p, slot, [&](int64_t heap) __attribute__((always_inline)) {
+    replay_any_heap<0, 0>(p, c, heap);
+  });
 }
 
-// Lean-path kernel for one algorithm with RF free-table chunks in VGPRs.
-template <int ALGO, int RF>
+// Lean path with RF free-table chunks in VGPRs; each heap runs the code of
+// its own algorithm.
+template <int RF>
 __global__ void __launch_bounds__(1024) lean_kernel(ReplayParams p) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   const uint32_t wave = uniform(threadIdx.x >> 6);  // the same in every lane of the wave
@@ -167,23 +167,21 @@ __global__ void __launch_bounds__(1024) lean_kernel(ReplayParams p) {
   // LDS bytes, then this wave's spill slot
   const Cold c = general_tiers(p, mine, slot);
   for_each_heap(p, slot, [&](int64_t heap) __attribute__((always_inline)) {
-    lean_one_heap<ALGO, RF>(p, lds, c, heap);
+    switch (p.algo[heap]) {
+      case kFirstFit: lean_one_heap<kFirstFit, RF>(p, lds, c, heap); break;
+      case kNextFit: lean_one_heap<kNextFit, RF>(p, lds, c, heap); break;
+      case kBestFit: lean_one_heap<kBestFit, RF>(p, lds, c, heap); break;
+      default: lean_one_heap<kSegFit, RF>(p, lds, c, heap); break;
+    }
   });
 }
 
-// Kernel sets: rf = free-table chunks in VGPRs (0 = general path).
+// Kernels by free-table chunks in VGPRs (0 = general path).
 struct KernelSet {
   int rf;
-  const void* fn[4];
+  const void* fn;
 };
-#define HDA_LEAN(RF)                                                                    \
-  {RF, {(const void*)lean_kernel<kFirstFit, RF>, (const void*)lean_kernel<kNextFit, RF>, \
-        (const void*)lean_kernel<kBestFit, RF>, (const void*)lean_kernel<kSegFit, RF>}}
-const KernelSet kSets[] = {
-    {0, {(const void*)general_kernel<kFirstFit>, (const void*)general_kernel<kNextFit>,
-         (const void*)general_kernel<kBestFit>, (const void*)general_kernel<kSegFit>}},
-    HDA_LEAN(4)};
-#undef HDA_LEAN
+const KernelSet kSets[] = {{0, (const void*)general_kernel}, {4, (const void*)lean_kernel<4>}};
 constexpr int kDefaultRF = 4;
 
 const KernelSet* find_set(int rf) {
@@ -195,14 +193,10 @@ const KernelSet* find_set(int rf) {
 struct DeviceCtx {
   int cus = 0;
   size_t max_lds = 0;
-  std::mutex enqueue;  // one fork/join sequence at a time on the shared streams
-  hipStream_t side[4] = {};
-  hipEvent_t fork = nullptr, join[4] = {};
   bool ok = false;
 };
 
-// Per-device properties and the library's fork/join streams (default
-// priority), created on first use.
+// Per-device properties, read on first use.
 DeviceCtx* device_ctx() {
   static std::mutex mu;
   static std::vector<DeviceCtx*> ctxs;
@@ -216,10 +210,7 @@ DeviceCtx* device_ctx() {
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
       c->cus = prop.multiProcessorCount;
       c->max_lds = std::max<size_t>(prop.sharedMemPerBlock, prop.maxSharedMemoryPerMultiProcessor);
-      c->ok = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) == hipSuccess;
-      for (int a = 0; a < 4 && c->ok; ++a)
-        c->ok = hipStreamCreateWithFlags(&c->side[a], hipStreamNonBlocking) == hipSuccess &&
-                hipEventCreateWithFlags(&c->join[a], hipEventDisableTiming) == hipSuccess;
+      c->ok = true;
     }
     ctxs[dev] = c;
   }
@@ -228,11 +219,11 @@ DeviceCtx* device_ctx() {
 
 uint32_t round64(int64_t x) { return (uint32_t)((x + 63) / 64 * 64); }
 
-// Launch geometry and tiers of the per-algorithm launches.
+// Launch geometry and tiers of the replay kernel.
 struct Pass {
   uint32_t W = 1, kf = 0, kl = 0, sf = 0, sl = 0, lds_wave = 0, lds_group = 0;
-  int64_t groups[4] = {1, 1, 1, 1}, slots[4] = {1, 1, 1, 1};
-  size_t off_free[4] = {}, off_stamp[4] = {}, off_live[4] = {};
+  int64_t groups = 1, slots = 1;
+  size_t off_free = 0, off_stamp = 0, off_live = 0;
 };
 
 struct Plan {
@@ -290,12 +281,10 @@ bool make_plan(const hda_batch_desc* d, bool persistent, Plan* pl) {
   m.lds_wave = m.kf * 12u + m.kl * 8u;
   m.lds_group = m.lds_wave * W;
   if (m.lds_group > dc->max_lds) return false;
-  for (int a = 0; a < 4; ++a) {
-    m.groups[a] = persistent ? occupancy_groups(set->fn[a], W, m.lds_group, dc->cus, tu.groups,
-                                                d->n_heaps)
-                             : 1;
-    m.slots[a] = m.groups[a] * W;
-  }
+  m.groups = persistent ? occupancy_groups(set->fn, W, m.lds_group, dc->cus, tu.groups,
+                                           d->n_heaps)
+                        : 1;
+  m.slots = m.groups * W;
   pl->set = set;
   pl->lean = lean;
   pl->capF = capF;
@@ -306,11 +295,9 @@ bool make_plan(const hda_batch_desc* d, bool persistent, Plan* pl) {
   pl->off_queues = off; off = align_up(off + kQueueWords * 4);
   const size_t H1 = (size_t)std::max<int64_t>(d->n_heaps, 1);
   pl->off_lists = off; off = align_up(off + (size_t)kClasses * H1 * 4);
-  for (int a = 0; a < 4; ++a) {
-    m.off_free[a] = off; off = align_up(off + (size_t)m.slots[a] * m.sf * 8);
-    m.off_stamp[a] = off; off = align_up(off + (size_t)m.slots[a] * m.sf * 4);
-    m.off_live[a] = off; off = align_up(off + (size_t)m.slots[a] * m.sl * 8);
-  }
+  m.off_free = off; off = align_up(off + (size_t)m.slots * m.sf * 8);
+  m.off_stamp = off; off = align_up(off + (size_t)m.slots * m.sf * 4);
+  m.off_live = off; off = align_up(off + (size_t)m.slots * m.sl * 8);
   pl->bytes = off;
   return true;
 }
@@ -336,8 +323,8 @@ ClassifyParams classify_params(const hda_batch_desc* d, const Plan& pl) {
   return q;
 }
 
-// Parameters of the launch for algorithm a.
-ReplayParams replay_params(const hda_batch_desc* d, const Plan& pl, int a) {
+// Parameters of the replay launch.
+ReplayParams replay_params(const hda_batch_desc* d, const Plan& pl) {
   const Pass& ps = pl.main;
   ReplayParams p;
   std::memset(&p, 0, sizeof(p));
@@ -347,13 +334,13 @@ ReplayParams replay_params(const hda_batch_desc* d, const Plan& pl, int a) {
   p.status = d->status;
   uint8_t* ws = static_cast<uint8_t*>(d->workspace);
   uint32_t* queues = reinterpret_cast<uint32_t*>(ws + pl.off_queues);
-  p.list = reinterpret_cast<const int32_t*>(ws + pl.off_lists) + (int64_t)a * d->n_heaps;
-  p.count = reinterpret_cast<const uint32_t*>(ws + pl.off_counts) + a;
-  p.queue = queues + a;
+  p.list = reinterpret_cast<const int32_t*>(ws + pl.off_lists) + (int64_t)kValid * d->n_heaps;
+  p.count = reinterpret_cast<const uint32_t*>(ws + pl.off_counts) + kValid;
+  p.queue = queues;
   p.migrated = queues + kMigrated;
-  p.spill_free = reinterpret_cast<Ent*>(ws + ps.off_free[a]);
-  p.spill_stamp = reinterpret_cast<uint32_t*>(ws + ps.off_stamp[a]);
-  p.spill_live = reinterpret_cast<Ent*>(ws + ps.off_live[a]);
+  p.spill_free = reinterpret_cast<Ent*>(ws + ps.off_free);
+  p.spill_stamp = reinterpret_cast<uint32_t*>(ws + ps.off_stamp);
+  p.spill_live = reinterpret_cast<Ent*>(ws + ps.off_live);
   p.n_heaps = d->n_heaps;
   p.first = 0;
   p.cap_free = pl.capF; p.cap_live = pl.capL;
@@ -370,11 +357,7 @@ bool set_lds_attr(const void* fn, uint32_t bytes) {
          hipSuccess;
 }
 
-bool set_lds_attrs(const Plan& pl) {
-  for (int a = 0; a < 4; ++a)
-    if (!set_lds_attr(pl.set->fn[a], pl.main.lds_group)) return false;
-  return true;
-}
+bool set_lds_attrs(const Plan& pl) { return set_lds_attr(pl.set->fn, pl.main.lds_group); }
 
 hipError_t launch(const void* fn, dim3 grid, dim3 block, uint32_t lds, hipStream_t st,
                   ReplayParams& p) {
@@ -388,21 +371,14 @@ int classify(const hda_batch_desc* d, const Plan& pl, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? HDA_OK : HDA_E_DEVICE;
 }
 
-// Classify, then the per-algorithm launches on the library's side streams,
-// forked from and joined back to s.  The caller holds dc->enqueue.
-int enqueue(const hda_batch_desc* d, const Plan& pl, DeviceCtx* dc, hipStream_t s) {
+// Classify, then the persistent replay kernel, both on s.
+int enqueue(const hda_batch_desc* d, const Plan& pl, hipStream_t s) {
   int rc = classify(d, pl, s);
   if (rc != HDA_OK) return rc;
-  if (hipEventRecord(dc->fork, s) != hipSuccess) return HDA_E_DEVICE;
-  for (int a = 0; a < 4; ++a) {
-    ReplayParams p = replay_params(d, pl, a);
-    if (hipStreamWaitEvent(dc->side[a], dc->fork, 0) != hipSuccess ||
-        launch(pl.set->fn[a], dim3((uint32_t)pl.main.groups[a]), dim3(64 * pl.main.W),
-               pl.main.lds_group, dc->side[a], p) != hipSuccess ||
-        hipEventRecord(dc->join[a], dc->side[a]) != hipSuccess ||
-        hipStreamWaitEvent(s, dc->join[a], 0) != hipSuccess)
-      return HDA_E_DEVICE;
-  }
+  ReplayParams p = replay_params(d, pl);
+  if (launch(pl.set->fn, dim3((uint32_t)pl.main.groups), dim3(64 * pl.main.W),
+             pl.main.lds_group, s, p) != hipSuccess)
+    return HDA_E_DEVICE;
   return hipGetLastError() == hipSuccess ? HDA_OK : HDA_E_DEVICE;
 }
 
@@ -424,7 +400,7 @@ int hda_replay_resolve(const hda_batch_desc* d, hda_tuning* out) {
   out->reg_live = -1;
   out->lds_free = pl.main.kf > 0 ? (int32_t)pl.main.kf : -1;
   out->lds_live = pl.main.kl > 0 ? (int32_t)pl.main.kl : -1;
-  out->groups = (int32_t)pl.main.groups[0];
+  out->groups = (int32_t)pl.main.groups;
   return HDA_OK;
 }
 
@@ -433,11 +409,9 @@ int hda_replay(const hda_batch_desc* d, void* stream) {
   if (!desc_ok(d) || !make_plan(d, true, &pl)) return HDA_E_INVAL;
   if (d->n_heaps == 0) return HDA_OK;
   if (!d->workspace || d->workspace_bytes < pl.bytes) return HDA_E_RANGE;
-  DeviceCtx* dc = device_ctx();
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (!dc || !set_lds_attrs(pl)) return HDA_E_DEVICE;
-  std::lock_guard<std::mutex> g(dc->enqueue);
-  return enqueue(d, pl, dc, s);
+  if (!set_lds_attrs(pl)) return HDA_E_DEVICE;
+  return enqueue(d, pl, s);
 }
 
 int hda_replay_per_heap(const hda_batch_desc* d, void* stream) {
@@ -449,22 +423,20 @@ int hda_replay_per_heap(const hda_batch_desc* d, void* stream) {
   if (!set_lds_attrs(pl)) return HDA_E_DEVICE;
   int rc = classify(d, pl, s);
   if (rc != HDA_OK) return rc;
-  // the host needs each heap's algorithm to pick the kernel it launches
+  // the host needs the number of valid heaps to launch one kernel per heap
   uint32_t counts[kClasses];
   const uint8_t* ws = static_cast<const uint8_t*>(d->workspace);
   if (hipMemcpyAsync(counts, ws + pl.off_counts, sizeof(counts), hipMemcpyDeviceToHost, s) !=
           hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return HDA_E_DEVICE;
-  for (int a = 0; a < 4; ++a) {
-    ReplayParams p = replay_params(d, pl, a);
-    p.use_queue = 0;
-    p.n_heaps = 1;
-    for (uint32_t k = 0; k < counts[a]; ++k) {
-      p.first = k;
-      if (launch(pl.set->fn[a], dim3(1), dim3(64), pl.main.lds_group, s, p) != hipSuccess)
-        return HDA_E_DEVICE;
-    }
+  ReplayParams p = replay_params(d, pl);
+  p.use_queue = 0;
+  p.n_heaps = 1;
+  for (uint32_t k = 0; k < counts[kValid]; ++k) {
+    p.first = k;
+    if (launch(pl.set->fn, dim3(1), dim3(64), pl.main.lds_group, s, p) != hipSuccess)
+      return HDA_E_DEVICE;
   }
   return hipGetLastError() == hipSuccess ? HDA_OK : HDA_E_DEVICE;
 }
@@ -513,7 +485,7 @@ int hda_replay_autotune(const hda_batch_desc* d, int32_t sample_heaps, void* str
     return HDA_E_DEVICE;
   // sample: the longest heaps, as many as the device holds at once under the
   // default tuning, each trace cut to its first kCut requests
-  const int64_t want = sample_heaps > 0 ? sample_heaps : pl.main.slots[0];
+  const int64_t want = sample_heaps > 0 ? sample_heaps : pl.main.slots;
   const std::vector<int32_t> sample = longest_heaps(off, want, dc->cus, kBudget, kCut);
   const int64_t S = (int64_t)sample.size();
   std::vector<int64_t> s_off(S + 1, 0), s_arena(S), s_align(S);
@@ -634,16 +606,14 @@ int hda_replay_capture(const hda_batch_desc* d, hda_graph** out) {
   Plan pl;
   if (!out || !desc_ok(d) || !make_plan(d, true, &pl) || d->n_heaps == 0) return HDA_E_INVAL;
   if (!d->workspace || d->workspace_bytes < pl.bytes) return HDA_E_RANGE;
-  DeviceCtx* dc = device_ctx();
-  if (!dc || !set_lds_attrs(pl)) return HDA_E_DEVICE;
+  if (!set_lds_attrs(pl)) return HDA_E_DEVICE;
   hipStream_t cs = nullptr;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return HDA_E_DEVICE;
   hda_graph* g = new hda_graph;
   int rc = HDA_E_DEVICE;
   {
-    std::lock_guard<std::mutex> lk(dc->enqueue);
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-      const int erc = enqueue(d, pl, dc, cs);
+      const int erc = enqueue(d, pl, cs);
       const hipError_t ec = hipStreamEndCapture(cs, &g->graph);
       if (erc == HDA_OK && ec == hipSuccess &&
           hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) == hipSuccess)
