@@ -77,8 +77,8 @@ enum {
  *     len_k, then the block addresses from list head to tail.
  */
 /* Where each heap's tables live.  Default (lean) path: the first
- * 64*reg_free free-table entries are held in vector registers (reg_free = 4;
- * 0 = 4), the next lds_free free entries and lds_live live entries in
+ * 64*reg_free free-table entries are held in vector registers (reg_free = 1,
+ * 2 or 4; 0 = 4), the next lds_free free entries and lds_live live entries in
  * LDS (defaults 128 and 1024).  A heap whose tables outgrow these tiers
  * before reaching meta_free / meta_live moves them, mid-trace, into the
  * general path's layout (LDS, then device memory in the workspace) and

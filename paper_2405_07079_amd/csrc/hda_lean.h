@@ -35,11 +35,17 @@ constexpr uint32_t kStampLimit = 1u << kKeyShift;
 
 __device__ __forceinline__ uint32_t wave_max(uint32_t v) { return ~wave_min(~v); }
 
+// Lane l of chunk r (both wave-uniform): every chunk's lane l is read and
+// the right one chosen on the scalar unit, which keeps the read free of
+// branches (a vector select chain here was turned into a branch ladder).
 template <int R>
-__device__ __forceinline__ uint32_t reg_pick(const uint32_t (&v)[R], uint32_t r) {
-  uint32_t x = opaque(v[0]);
+__device__ __forceinline__ uint32_t reg_lane(const uint32_t (&v)[R], uint32_t r, uint32_t l) {
+  uint32_t x = rdlane(v[0], l);
 #pragma unroll
-  for (int k = 1; k < R; ++k) x = (r == (uint32_t)k) ? opaque(v[k]) : x;
+  for (int k = 1; k < R; ++k) {
+    const uint32_t y = rdlane(v[k], l);
+    x = (r == (uint32_t)k) ? y : x;
+  }
   return x;
 }
 // Lane l of chunk r becomes x; nothing changes when r >= R.
@@ -92,16 +98,16 @@ struct LeanHeap {
 
   // ---- free-table entries by wave-uniform index ----
   __device__ __forceinline__ uint32_t size_at(uint32_t j) {
-    if (j < HF) return rdlane(reg_pick(fs, j >> 6), j & 63u);
+    if (j < HF) return reg_lane(fs, j >> 6, j & 63u);
     wave_sync();
     return uniform(ent_s(m.cf[j - HF]));
   }
   __device__ __forceinline__ void read(uint32_t j, uint32_t& a, uint32_t& s, uint32_t& k) {
     if (j < HF) {
       const uint32_t r = j >> 6, l = j & 63u;
-      a = rdlane(reg_pick(fa, r), l);
-      s = rdlane(reg_pick(fs, r), l);
-      k = kSeg ? rdlane(reg_pick(fk, r), l) : 0u;
+      a = reg_lane(fa, r, l);
+      s = reg_lane(fs, r, l);
+      k = kSeg ? reg_lane(fk, r, l) : 0u;
     } else {
       wave_sync();
       const Ent e = m.cf[j - HF];

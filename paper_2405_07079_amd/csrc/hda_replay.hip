@@ -181,7 +181,10 @@ struct KernelSet {
   int rf;
   const void* fn;
 };
-const KernelSet kSets[] = {{0, (const void*)general_kernel}, {4, (const void*)lean_kernel<4>}};
+const KernelSet kSets[] = {{0, (const void*)general_kernel},
+                           {1, (const void*)lean_kernel<1>},
+                           {2, (const void*)lean_kernel<2>},
+                           {4, (const void*)lean_kernel<4>}};
 constexpr int kDefaultRF = 4;
 
 const KernelSet* find_set(int rf) {

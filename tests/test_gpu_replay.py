@@ -154,7 +154,7 @@ def test_uneven_batch_reduced():
     check_against_oracle(b, res, states, status, heaps)
 
 
-@pytest.mark.parametrize("bad", (dict(reg_free=3), dict(reg_free=6), dict(reg_live=4),
+@pytest.mark.parametrize("bad", (dict(reg_free=3), dict(reg_free=8), dict(reg_live=4),
                                  dict(lds_free=100),
                                  dict(heaps_per_group=17), dict(lds_live=1 << 20)))
 def test_bad_tuning_is_rejected(bad):
