@@ -78,15 +78,17 @@ enum {
  */
 /* Where each heap's tables live.  Default (lean) path: the first
  * 64*reg_free free-table entries are held in vector registers (reg_free = 1,
- * 2 or 4; 0 = 4), the next lds_free free entries and lds_live live entries in
- * LDS (defaults 128 and 1024).  A heap whose tables outgrow these tiers
- * before reaching meta_free / meta_live moves them, mid-trace, into the
- * general path's layout (LDS, then device memory in the workspace) and
- * continues there; results do not depend on the tuning.  reg_free = -1 selects the general path for every heap: no
- * registers, lds_free / lds_live entries in LDS (defaults 64 and 1024), the
- * rest in device memory (workspace).  reg_live must be 0 or -1 (the live
- * table is never held in registers).  0 = default for every field; -1 = none
- * of that storage.  Any other value is E_INVAL. */
+ * 2 or 4; 0 = 2); the rest of the free table and the whole live table share
+ * one LDS pool per heap of lds_free * 16 + lds_live * 8 bytes (defaults 128
+ * and 1024: 10 KiB), free entries from its start and live entries from its
+ * end.  A heap whose tables outgrow the pool before reaching meta_free /
+ * meta_live moves them, mid-trace, to the general path in its device-memory
+ * slot of the workspace and continues there; results do not depend on the
+ * tuning.  reg_free = -1 selects the general path for every heap: no
+ * registers, lds_free free and lds_live live entries in LDS (defaults 64 and
+ * 1024), the rest in device memory (workspace).  reg_live must be 0 or -1
+ * (the live table is never held in registers).  0 = default for every
+ * field; -1 = none of that storage.  Any other value is E_INVAL. */
 typedef struct hda_tuning {
   int32_t heaps_per_group; /* waves (= heaps in flight) per workgroup (1..16)  */
   int32_t reg_free;        /* free-table 64-entry chunks in registers          */

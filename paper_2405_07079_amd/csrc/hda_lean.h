@@ -1,7 +1,9 @@
 // Lean replay core: one wavefront replays one heap with exactly two storage
 // tiers.  Free-table entry i lives in lane i % 64 of 64-entry chunk i / 64;
-// the first RF chunks are VGPRs and the rest, up to kf entries, LDS.  The
-// live table is in LDS.  Selection (Sec. II, Sec. IV, Sec. V-A) and the
+// the first RF chunks are VGPRs and the rest LDS.  The wave's LDS region is
+// one pool shared by both tables: free chunks from its start, live entries
+// from its end, so a heap with many free blocks and one with many live
+// blocks both fit.  Selection (Sec. II, Sec. IV, Sec. V-A) and the
 // neighbour search of coalescing (Alg. 2, Alg. 5) are wave-wide scans over the
 // chunks followed by one DPP reduction.
 //
@@ -10,7 +12,7 @@
 // (no block starts or ends at granule ~0), so every scan covers whole chunks
 // with no bounds mask.
 //
-// When a table would outgrow these tiers before it reaches the capacity the
+// When the tables would outgrow the pool before reaching the capacities the
 // caller asked for, the request stops with kOverflow (changing nothing), the
 // tables move into the general core's layout (hda_core.h, whose tables
 // continue into device memory) and the heap goes on there.  Results are the
@@ -56,11 +58,16 @@ __device__ __forceinline__ void reg_place(uint32_t (&v)[R], uint32_t r, uint32_t
   for (int k = 0; k < R; ++k) v[k] = (me && r == (uint32_t)k) ? x : v[k];
 }
 
+// The wave's LDS pool: `bytes` (a multiple of 16) from `base`.
 struct LeanLds {
-  HDA_LDS Ent* cf;        // free entries 64*RF .. 64*RF + kf - 1
-  HDA_LDS uint32_t* ck;   // their segregated-fit keys
-  HDA_LDS Ent* lv;        // live entries 0 .. kl - 1
-  uint32_t kf, kl;
+  HDA_LDS uint8_t* base;
+  uint32_t bytes;
+};
+
+// A segregated-fit free entry in LDS: block and key in one 16-byte record
+// (one 128-bit load); the other algorithms store just the 8-byte block.
+struct __attribute__((aligned(16))) SegRec {
+  uint32_t a, s, k, pad;
 };
 
 template <int ALGO, int RF>
@@ -75,17 +82,43 @@ struct LeanHeap {
   int64_t arena;
   uint32_t shift, ag;
   uint32_t F, L, rover, clock;
-  uint32_t limF, limL;            // F and L never exceed these
-  bool metaF, metaL;              // the limit is the caller's capacity (E_NOMETA), not the tiers
+  uint32_t capF, capL;            // the caller's capacities (E_NOMETA past them)
 
-  __device__ __forceinline__ LeanHeap(const LeanLds& lds, const HeapRegs& h, uint32_t capF,
-                                      uint32_t capL)
-      : m(lds), arena(h.arena), shift(h.shift), ag(h.ag) {
-    const uint32_t fastF = HF + lds.kf, fastL = lds.kl;
-    limF = capF < fastF ? capF : fastF;
-    limL = capL < fastL ? capL : fastL;
-    metaF = capF <= fastF;
-    metaL = capL <= fastL;
+  __device__ __forceinline__ LeanHeap(const LeanLds& lds, const HeapRegs& h, uint32_t cap_free,
+                                      uint32_t cap_live)
+      : m(lds), arena(h.arena), shift(h.shift), ag(h.ag), capF(cap_free), capL(cap_live) {}
+
+  // ---- the LDS pool ----
+  static constexpr uint32_t kRec = kSeg ? 16u : 8u;  // bytes per free entry in LDS
+  // Pool bytes the tables take with f free and l live entries: the free
+  // entries past the register chunks in whole 64-entry chunks (scans read
+  // whole chunks), then the live entries.
+  __device__ __forceinline__ uint32_t need_bytes(uint32_t f, uint32_t l) const {
+    const uint32_t cold = f > HF ? f - HF : 0u;
+    return ((cold + 63u) & ~63u) * kRec + l * 8u;
+  }
+  // LDS free entry i (free-table index HF + i).
+  __device__ __forceinline__ void cold_get(uint32_t i, uint32_t& a, uint32_t& s,
+                                           uint32_t& k) const {
+    if constexpr (kSeg) {
+      const HDA_LDS SegRec* r = (HDA_LDS SegRec*)m.base + i;
+      a = r->a; s = r->s; k = r->k;
+    } else {
+      const Ent e = ((HDA_LDS Ent*)m.base)[i];
+      a = ent_a(e); s = ent_s(e); k = 0u;
+    }
+  }
+  __device__ __forceinline__ void cold_put(uint32_t i, uint32_t a, uint32_t s, uint32_t k) const {
+    if constexpr (kSeg) {
+      HDA_LDS SegRec* r = (HDA_LDS SegRec*)m.base + i;
+      r->a = a; r->s = s; r->k = k; r->pad = 0u;
+    } else {
+      ((HDA_LDS Ent*)m.base)[i] = mk_ent(a, s);
+    }
+  }
+  // Live entry i, counted from the end of the pool.
+  __device__ __forceinline__ HDA_LDS Ent* live_ptr(uint32_t i) const {
+    return (HDA_LDS Ent*)(m.base + m.bytes) - (i + 1u);
   }
 
   __device__ __forceinline__ uint32_t byte_class(uint32_t sg) const {
@@ -100,7 +133,9 @@ struct LeanHeap {
   __device__ __forceinline__ uint32_t size_at(uint32_t j) {
     if (j < HF) return reg_lane(fs, j >> 6, j & 63u);
     wave_sync();
-    return uniform(ent_s(m.cf[j - HF]));
+    uint32_t a, s, k;
+    cold_get(j - HF, a, s, k);
+    return uniform(s);
   }
   __device__ __forceinline__ void read(uint32_t j, uint32_t& a, uint32_t& s, uint32_t& k) {
     if (j < HF) {
@@ -110,10 +145,11 @@ struct LeanHeap {
       k = kSeg ? reg_lane(fk, r, l) : 0u;
     } else {
       wave_sync();
-      const Ent e = m.cf[j - HF];
-      a = uniform(ent_a(e));
-      s = uniform(ent_s(e));
-      k = kSeg ? uniform(m.ck[j - HF]) : 0u;
+      uint32_t ea, es, ek;
+      cold_get(j - HF, ea, es, ek);
+      a = uniform(ea);
+      s = uniform(es);
+      k = kSeg ? uniform(ek) : 0u;
     }
   }
   // The register chunks take a select each (none matches a cold index), so
@@ -128,8 +164,7 @@ struct LeanHeap {
     if (kSeg) reg_place(fk, r, l, k);
     if (j >= HF) {
       wave_sync();
-      m.cf[j - HF] = mk_ent(a, s);
-      if (kSeg) m.ck[j - HF] = k;
+      cold_put(j - HF, a, s, k);
     }
   }
   __device__ __forceinline__ void clear(uint32_t j) { write(j, kNone, 0u, 0u); }
@@ -137,13 +172,13 @@ struct LeanHeap {
   // ---- live table ----
   __device__ __forceinline__ void live_read(uint32_t i, uint32_t& a, uint32_t& s) {
     wave_sync();
-    const Ent e = m.lv[i];
+    const Ent e = *live_ptr(i);
     a = uniform(ent_a(e));
     s = uniform(ent_s(e));
   }
   __device__ __forceinline__ void live_write(uint32_t i, uint32_t a, uint32_t s) {
     wave_sync();
-    m.lv[i] = mk_ent(a, s);  // every lane, same value (see write())
+    *live_ptr(i) = mk_ent(a, s);  // every lane, same value (see write())
   }
 
   // Visit every chunk holding entries: f(chunk, a, s, key).  LDS chunks are
@@ -156,22 +191,18 @@ struct LeanHeap {
     for (; 64u * (c + 3u) < F; c += 4u) {
       const uint32_t i = 64u * (c - RF) + lane_id();
       wave_sync();
-      Ent e[4];
-      uint32_t k[4];
+      uint32_t ea[4], es[4], ek[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        e[u] = m.cf[i + 64u * u];
-        k[u] = kSeg ? m.ck[i + 64u * u] : 0u;
-      }
+      for (int u = 0; u < 4; ++u) cold_get(i + 64u * u, ea[u], es[u], ek[u]);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) f(c + u, ent_a(e[u]), ent_s(e[u]), k[u]);
+      for (int u = 0; u < 4; ++u) f(c + u, ea[u], es[u], ek[u]);
     }
     for (; 64u * c < F; ++c) {
       const uint32_t i = 64u * (c - RF) + lane_id();
       wave_sync();
-      const Ent e = m.cf[i];
-      const uint32_t k = kSeg ? m.ck[i] : 0u;
-      f(c, ent_a(e), ent_s(e), k);
+      uint32_t ea, es, ek;
+      cold_get(i, ea, es, ek);
+      f(c, ea, es, ek);
     }
   }
 
@@ -179,11 +210,6 @@ struct LeanHeap {
   __device__ __forceinline__ void init() {
 #pragma unroll
     for (int k = 0; k < RF; ++k) { fa[k] = kNone; fs[k] = 0u; fk[k] = 0u; }
-    wave_sync();
-    for (uint32_t i = lane_id(); i < m.kf; i += 64u) {
-      m.cf[i] = mk_ent(kNone, 0u);
-      if (kSeg) m.ck[i] = 0u;
-    }
     F = 1; L = 0; rover = 0; clock = 1; cnt = 0;
     write(0, 0u, ag, kSeg ? seg_key(ag) : 0u);
     if (kSeg) cnt_add(byte_class(ag), 1);
@@ -293,7 +319,8 @@ struct LeanHeap {
   __device__ __forceinline__ int64_t alloc(uint32_t sg, uint32_t kreq) {
     uint32_t j, a, s;
     if (!select(sg, kreq, j, a, s)) return kFail;
-    if (L >= limL) return metaL ? kENoMeta : kOverflow;
+    if (L >= capL) return kENoMeta;
+    if (need_bytes(F, L + 1u) > m.bytes) return kOverflow;
     if (s > sg) {  // Alg. 1 / Alg. 4: the block is cut from the low end
       if (kSeg && clock >= kStampLimit) return kOverflow;
       write(j, a + sg, s - sg, kSeg ? seg_key(s - sg) : 0u);
@@ -326,7 +353,13 @@ struct LeanHeap {
       cr = ir ? c : cr;
     });
     if ((ML | MR) == 0ull) {
-      if (F >= limF) return metaF ? kENoMeta : kOverflow;
+      if (F >= capF) return kENoMeta;
+      // (the freed block still counts as live here: the check is on the safe side)
+      if (need_bytes(F + 1u, L) > m.bytes) return kOverflow;
+      if (F >= HF && ((F - HF) & 63u) == 0u) {  // a new LDS chunk: its slots start empty
+        wave_sync();
+        cold_put(F - HF + lane_id(), kNone, 0u, 0u);
+      }
       write(F, x, sz, kSeg ? seg_key(sz) : 0u);
       if (kSeg) cnt_add(byte_class(sz), 1);
       ++F;
@@ -382,28 +415,34 @@ struct LeanHeap {
     return free_index((uint32_t)(((uint64_t)r * (uint64_t)L) >> 32));
   }
 
-  // Hand this heap over to the general core (hda_core.h, no register
-  // chunks) built on the same LDS bytes: general free entry i is LDS slot i
-  // while i < kf and device slot i - kf after, with its push stamp beside it;
-  // the live table is already where the general core keeps it.  Free entry i
-  // moves from lean LDS slot i - 64*RF (or a register chunk) to general slot
-  // i, i.e. towards higher LDS slots, so chunks are moved last first.
+  // Hand this heap over to the general core (hda_core.h) on tiers `c` with
+  // no LDS part: every free entry i goes to device slot i with its push stamp
+  // beside it, every live entry i to device slot i.
   __device__ void migrate(const Cold& c, HeapRegs& h) {
     const uint32_t lane = lane_id();
-    const uint32_t nch = (F + 63u) >> 6;
-    for (uint32_t ch = nch; ch-- > (uint32_t)RF;) {
-      const uint32_t src = 64u * (ch - RF) + lane, gi = 64u * ch + lane;
+    for (uint32_t ch = RF; 64u * ch < F; ++ch) {
+      const uint32_t gi = 64u * ch + lane;
       wave_sync();
-      const Ent e = m.cf[src];
-      const uint32_t st = kSeg ? m.ck[src] & (kStampLimit - 1u) : 0u;
-      wave_sync();
-      if (gi < F) put_free(c, gi, e, st);
+      uint32_t a, s, k;
+      cold_get(64u * (ch - RF) + lane, a, s, k);
+      if (gi < F) {
+        c.gf[gi] = mk_ent(a, s);
+        if (kSeg) c.gst[gi] = k & (kStampLimit - 1u);
+      }
     }
 #pragma unroll
-    for (int k = RF - 1; k >= 0; --k) {
+    for (int k = 0; k < RF; ++k) {
       const uint32_t gi = 64u * (uint32_t)k + lane;
+      if (gi < F) {
+        c.gf[gi] = mk_ent(fa[k], fs[k]);
+        if (kSeg) c.gst[gi] = fk[k] & (kStampLimit - 1u);
+      }
+    }
+    for (uint32_t base = 0; base < L; base += 64u) {
+      const uint32_t i = base + lane;
       wave_sync();
-      if (gi < F) put_free(c, gi, mk_ent(fa[k], fs[k]), kSeg ? fk[k] & (kStampLimit - 1u) : 0u);
+      const Ent e = *live_ptr(i < L ? i : 0u);
+      if (i < L) c.gl[i] = e;
     }
     wave_sync();
     h.F = F;
@@ -411,15 +450,6 @@ struct LeanHeap {
     h.rover = rover;
     h.clock = clock;
     h.cnt = cnt;
-  }
-  __device__ static __forceinline__ void put_free(const Cold& c, uint32_t gi, Ent e, uint32_t st) {
-    if (gi < c.kf) {
-      c.lf[gi] = e;
-      if (kSeg) c.lst[gi] = st;
-    } else {
-      c.gf[gi - c.kf] = e;
-      if (kSeg) c.gst[gi - c.kf] = st;
-    }
   }
 
   // Canonical state, same format as the general core (hda.h).
@@ -449,7 +479,7 @@ struct LeanHeap {
     for (uint32_t base = 0; base < L; base += 64u) {
       const uint32_t i = base + lane;
       wave_sync();
-      const Ent e = m.lv[i < L ? i : 0u];
+      const Ent e = *live_ptr(i < L ? i : 0u);
       if (i < L) {
         lo[1 + 2 * i] = (int64_t)((uint64_t)ent_a(e) << sh);
         lo[2 + 2 * i] = (int64_t)((uint64_t)ent_s(e) << sh);

@@ -158,13 +158,10 @@ __global__ void __launch_bounds__(1024) lean_kernel(ReplayParams p) {
   HDA_LDS uint8_t* mine = (HDA_LDS uint8_t*)smem + (size_t)wave * p.lds_wave_bytes;
   const uint64_t slot = (uint64_t)blockIdx.x * p.waves_per_group + wave;
   LeanLds lds;
-  lds.cf = (HDA_LDS Ent*)(mine);
-  lds.ck = (HDA_LDS uint32_t*)(mine + (size_t)p.kf * 8);
-  lds.lv = (HDA_LDS Ent*)(mine + (size_t)p.kf * 12);
-  lds.kf = p.kf;
-  lds.kl = p.kl;
-  // the general core's tiers for a heap that outgrows the lean ones: the same
-  // LDS bytes, then this wave's spill slot
+  lds.base = mine;
+  lds.bytes = p.lds_wave_bytes;
+  // the general core's tiers for a heap that outgrows the pool: this wave's
+  // device-memory slot (no LDS part)
   const Cold c = general_tiers(p, mine, slot);
   for_each_heap(p, slot, [&](int64_t heap) __attribute__((always_inline)) {
     switch (p.algo[heap]) {
@@ -185,7 +182,7 @@ const KernelSet kSets[] = {{0, (const void*)general_kernel},
                            {1, (const void*)lean_kernel<1>},
                            {2, (const void*)lean_kernel<2>},
                            {4, (const void*)lean_kernel<4>}};
-constexpr int kDefaultRF = 4;
+constexpr int kDefaultRF = 2;
 
 const KernelSet* find_set(int rf) {
   for (const KernelSet& s : kSets)
@@ -225,6 +222,7 @@ uint32_t round64(int64_t x) { return (uint32_t)((x + 63) / 64 * 64); }
 // Launch geometry and tiers of the replay kernel.
 struct Pass {
   uint32_t W = 1, kf = 0, kl = 0, sf = 0, sl = 0, lds_wave = 0, lds_group = 0;
+  uint32_t lds_free = 0, lds_live = 0;  // the LDS residency as the tuning states it
   int64_t groups = 1, slots = 1;
   size_t off_free = 0, off_stamp = 0, off_live = 0;
 };
@@ -272,16 +270,31 @@ bool make_plan(const hda_batch_desc* d, bool persistent, Plan* pl) {
   // LDS entries: 0 = default, -1 = none
   const uint32_t want_kf = tu.lds_free > 0 ? (uint32_t)tu.lds_free
                                            : (tu.lds_free < 0 ? 0u : (lean ? 128u : 64u));
+  // (lean: the pool, lds_free * 16 + lds_live * 8 bytes; general: LDS tiers)
   const uint32_t want_kl = tu.lds_live > 0 ? (uint32_t)tu.lds_live : (tu.lds_live < 0 ? 0u : 1024u);
   Pass& m = pl->main;
   m.W = W;
-  // LDS parts never exceed the capacities; the general core (a lean heap
-  // after migration, too) keeps entries past them in device memory
-  m.kf = std::min(want_kf, capF);
-  m.kl = std::min(want_kl, capL);
-  m.sf = capF - m.kf;
-  m.sl = capL - m.kl;
-  m.lds_wave = m.kf * 12u + m.kl * 8u;
+  if (lean) {
+    // one LDS pool per wave with room for want_kf segregated-fit free
+    // entries (16 B) and want_kl live entries (8 B); a heap that outgrows it
+    // continues on the general core in its device-memory slot
+    m.kf = m.kl = 0;
+    m.sf = capF;
+    m.sl = capL;
+    m.lds_wave = (want_kf * 16u + want_kl * 8u + 15u) & ~15u;
+    m.lds_free = want_kf;
+    m.lds_live = want_kl;
+  } else {
+    // LDS parts never exceed the capacities; entries past them are in device
+    // memory
+    m.kf = std::min(want_kf, capF);
+    m.kl = std::min(want_kl, capL);
+    m.sf = capF - m.kf;
+    m.sl = capL - m.kl;
+    m.lds_wave = m.kf * 12u + m.kl * 8u;
+    m.lds_free = m.kf;
+    m.lds_live = m.kl;
+  }
   m.lds_group = m.lds_wave * W;
   if (m.lds_group > dc->max_lds) return false;
   m.groups = persistent ? occupancy_groups(set->fn, W, m.lds_group, dc->cus, tu.groups,
@@ -401,8 +414,8 @@ int hda_replay_resolve(const hda_batch_desc* d, hda_tuning* out) {
   out->heaps_per_group = (int32_t)pl.main.W;
   out->reg_free = pl.set->rf > 0 ? pl.set->rf : -1;
   out->reg_live = -1;
-  out->lds_free = pl.main.kf > 0 ? (int32_t)pl.main.kf : -1;
-  out->lds_live = pl.main.kl > 0 ? (int32_t)pl.main.kl : -1;
+  out->lds_free = pl.main.lds_free > 0 ? (int32_t)pl.main.lds_free : -1;
+  out->lds_live = pl.main.lds_live > 0 ? (int32_t)pl.main.lds_live : -1;
   out->groups = (int32_t)pl.main.groups;
   return HDA_OK;
 }

@@ -36,9 +36,9 @@ def lib():
 def replay(batch, kf=64, kl=64, cf=4096, cl=4096, shape=2, overflowed=None):
     """Replay a workloads.Batch heap by heap in the emulator.  shape selects
     the core: general with 0 = no register part, 1 = (1, 2) chunks, 2 = (4, 8)
-    chunks; lean with 3 = one, 4 = four free chunks in registers (kf/kl are
-    then its LDS entries, and a heap that outgrows them is replayed again on
-    the general core).  kf/kl are the cold entries kept in "LDS"; cf/cl the
+    chunks; lean with 3 = one, 4 = four free chunks in registers (kf/kl then
+    size its LDS pool: room for kf 16-byte free and kl live entries; a heap
+    that outgrows it moves to the general core with no LDS part).  kf/kl are the cold entries kept in "LDS"; cf/cl the
     table capacities.  overflowed, if given, is a uint8 array of heaps that
     took the second pass."""
     H = batch.heaps

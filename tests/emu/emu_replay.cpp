@@ -95,6 +95,10 @@ extern "C" int emu_replay(int64_t H, const int64_t* arena, const int64_t* align,
   p.res = res; p.state = state; p.state_off = state_off; p.state_len = state_len;
   p.status = status;
   const bool lean = shape >= 3;
+  // lean core: an LDS pool with room for kf 16-byte free and kl live entries;
+  // the general core it may move to has no LDS part
+  const uint32_t pool = kf * 16u + kl * 8u;
+  if (lean) kf = kl = 0;
   const uint32_t hf = 64u * kShapeRF[shape], hl = 64u * kShapeRL[shape];
   const uint32_t coldF = cap_free > hf ? cap_free - hf : 0u;
   const uint32_t coldL = cap_live > hl ? cap_live - hl : 0u;
@@ -103,6 +107,7 @@ extern "C" int emu_replay(int64_t H, const int64_t* arena, const int64_t* align,
   p.cap_free = cap_free; p.cap_live = cap_live;
   p.kf = kf; p.kl = kl; p.sf = coldF - kf; p.sl = coldL - kl;
   std::vector<uint8_t> lds(size_t(kf) * 12 + size_t(kl) * 8 + 16);
+  std::vector<uint8_t> pool_mem(size_t(pool) + 16);
   uint32_t migrated = 0;
   p.migrated = &migrated;
   std::vector<Ent> gf(p.sf + 64), gl(p.sl + 64);
@@ -124,12 +129,10 @@ extern "C" int emu_replay(int64_t H, const int64_t* arena, const int64_t* align,
     c.kf = kf; c.kl = kl; c.cf = coldF; c.cl = coldL;
     uint64_t n_sync = 0;
     if (lean) {
+      std::memset(pool_mem.data(), 0xA5, pool_mem.size());
       LeanLds ll;
-      ll.cf = c.lf;
-      ll.ck = c.lst;
-      ll.lv = c.ll;
-      ll.kf = kf;
-      ll.kl = kl;
+      ll.base = pool_mem.data();
+      ll.bytes = pool;
       const uint32_t before = migrated;
       g_job = LaneJob{&p, &c, &ll, h, shape, 0};
       run_wave(w, stacks);

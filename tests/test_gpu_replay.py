@@ -264,7 +264,7 @@ def test_autotune_picks_a_valid_tuning():
     db = hda.upload(b)
     db.res.fill_(0x5a5a)
     tu = hda.hda_replay_autotune(db)
-    assert tu[1] == 4 and tu[3] > 0 and tu[4] > 0       # lean path, LDS tiers
+    assert tu[1] > 0 and tu[3] > 0 and tu[4] > 0        # lean path, LDS pool
     assert (db.res == 0x5a5a).all()                     # the caller's buffers are untouched
     hda.retune(db, tu)
     hda.hda_replay(db)
