@@ -297,7 +297,7 @@ def main():
                      # free and live tables stay in VGPRs and LDS for this workload
                      "metadata_hbm_bytes_per_request": 0,
                      "lds_bank_conflict_cycles_per_request": recorded_lds_conflicts(),
-                     "kernel": "lean_kernel<4>",
+                     "kernel": f"lean_kernel<{max(resolved['reg_free'], 0)}>",
                      "avg_launch_ms": avg_launch_s * 1e3,
                      "bytes_per_request": BYTES_PER_REQUEST,
                      "requests_per_launch": batch.requests},
