@@ -83,6 +83,7 @@ struct LeanHeap {
   uint32_t shift, ag;
   uint32_t F, L, rover, clock;
   uint32_t capF, capL;            // the caller's capacities (E_NOMETA past them)
+  uint32_t live_room;             // live entries the pool holds beside the current free chunks
 
   __device__ __forceinline__ LeanHeap(const LeanLds& lds, const HeapRegs& h, uint32_t cap_free,
                                       uint32_t cap_live)
@@ -96,6 +97,12 @@ struct LeanHeap {
   __device__ __forceinline__ uint32_t need_bytes(uint32_t f, uint32_t l) const {
     const uint32_t cold = f > HF ? f - HF : 0u;
     return ((cold + 63u) & ~63u) * kRec + l * 8u;
+  }
+  // Recompute live_room after F changed.
+  __device__ __forceinline__ void set_room() {
+    const uint32_t cold = F > HF ? F - HF : 0u;
+    const uint32_t used = ((cold + 63u) & ~63u) * kRec;
+    live_room = used <= m.bytes ? (m.bytes - used) >> 3 : 0u;
   }
   // LDS free entry i (free-table index HF + i).
   __device__ __forceinline__ void cold_get(uint32_t i, uint32_t& a, uint32_t& s,
@@ -211,6 +218,7 @@ struct LeanHeap {
 #pragma unroll
     for (int k = 0; k < RF; ++k) { fa[k] = kNone; fs[k] = 0u; fk[k] = 0u; }
     F = 1; L = 0; rover = 0; clock = 1; cnt = 0;
+    set_room();
     write(0, 0u, ag, kSeg ? seg_key(ag) : 0u);
     if (kSeg) cnt_add(byte_class(ag), 1);
   }
@@ -218,14 +226,15 @@ struct LeanHeap {
   // Remove free entry j: the last entry moves into its place and the last
   // slot is cleared.
   __device__ __forceinline__ void remove(uint32_t j) {
+    // no branch on j == last: moving the last entry onto itself is harmless,
+    // and a branch here made the compiler copy the register chunks
     const uint32_t last = F - 1u;
-    if (j != last) {
-      uint32_t a, s, k;
-      read(last, a, s, k);
-      write(j, a, s, k);
-    }
+    uint32_t a, s, k;
+    read(last, a, s, k);
+    write(j, a, s, k);
     clear(last);
     F = last;
+    set_room();
   }
 
   // Selection.  On success j is the chosen entry and (a, s) its block.
@@ -320,7 +329,7 @@ struct LeanHeap {
     uint32_t j, a, s;
     if (!select(sg, kreq, j, a, s)) return kFail;
     if (L >= capL) return kENoMeta;
-    if (need_bytes(F, L + 1u) > m.bytes) return kOverflow;
+    if (L >= live_room) return kOverflow;
     if (s > sg) {  // Alg. 1 / Alg. 4: the block is cut from the low end
       if (kSeg && clock >= kStampLimit) return kOverflow;
       write(j, a + sg, s - sg, kSeg ? seg_key(s - sg) : 0u);
@@ -363,6 +372,7 @@ struct LeanHeap {
       write(F, x, sz, kSeg ? seg_key(sz) : 0u);
       if (kSeg) cnt_add(byte_class(sz), 1);
       ++F;
+      set_room();
     } else if (MR == 0ull) {
       const uint32_t l = ctz64(ML), jl = 64u * rdlane(cl, l) + l;
       const uint32_t sl = size_at(jl);
@@ -397,6 +407,7 @@ struct LeanHeap {
         cnt_add(byte_class(ms), 1);
       }
       F = last;
+      set_room();
     }
     const uint32_t last = L - 1u;
     if (idx != last) {
