@@ -29,13 +29,16 @@
 namespace hda {
 
 constexpr int64_t kOverflow = -100;      // internal: the fast tiers are too small
-// Segregated-fit key of a free block: byte class in the top 6 bits, push
-// stamp below, so the head of class c (the block pushed last) is the largest
-// key under (c + 1) << 26.
+// Segregated-fit key of a free block: byte class in the top 6 bits and,
+// below, the push stamp taken from the all-ones value (kStampLimit - 1 -
+// stamp).  The smallest key at or above c << 26 is then the head (the block
+// pushed last) of the first non-empty class at or above c, so one wave-wide
+// minimum does Alg. 4's class search and list-head lookup together, and no
+// per-class counts are kept on the request path.  Stamps start at 1, so a
+// key never equals kNone, the key of an empty slot.
 constexpr uint32_t kKeyShift = 26;
 constexpr uint32_t kStampLimit = 1u << kKeyShift;
-
-__device__ __forceinline__ uint32_t wave_max(uint32_t v) { return ~wave_min(~v); }
+constexpr uint32_t kStampMask = kStampLimit - 1u;
 
 // Lane l of chunk r (both wave-uniform): every chunk's lane l is read and
 // the right one chosen on the scalar unit, which keeps the read free of
@@ -78,7 +81,6 @@ struct LeanHeap {
 
   LeanLds m;
   uint32_t fa[RF], fs[RF], fk[RF];
-  uint32_t cnt;                   // segregated fit: lane k = free blocks of byte class k
   int64_t arena;
   uint32_t shift, ag;
   uint32_t F, L, rover, clock;
@@ -131,9 +133,19 @@ struct LeanHeap {
   __device__ __forceinline__ uint32_t byte_class(uint32_t sg) const {
     return floor_log2_u32(sg) + shift;
   }
-  __device__ __forceinline__ uint32_t seg_key(uint32_t sg) { return (byte_class(sg) << kKeyShift) | clock++; }
-  __device__ __forceinline__ void cnt_add(uint32_t cls, int d) {
-    cnt += (lane_id() == cls) ? (uint32_t)d : 0u;
+  __device__ __forceinline__ uint32_t seg_key(uint32_t sg) {
+    return (byte_class(sg) << kKeyShift) | (clock++ ^ kStampMask);
+  }
+  // Lane k: the number of free blocks of byte class k (for the canonical
+  // state and the hand-over to the general core; not kept per request).
+  __device__ uint32_t class_counts() {
+    uint32_t n = 0;
+    for (uint32_t j = 0; j < F; ++j) {
+      uint32_t a, s, k;
+      read(j, a, s, k);
+      n += lane_id() == (k >> kKeyShift) ? 1u : 0u;
+    }
+    return n;
   }
 
   // ---- free-table entries by wave-uniform index ----
@@ -174,7 +186,7 @@ struct LeanHeap {
       cold_put(j - HF, a, s, k);
     }
   }
-  __device__ __forceinline__ void clear(uint32_t j) { write(j, kNone, 0u, 0u); }
+  __device__ __forceinline__ void clear(uint32_t j) { write(j, kNone, 0u, kNone); }
 
   // ---- live table ----
   __device__ __forceinline__ void live_read(uint32_t i, uint32_t& a, uint32_t& s) {
@@ -216,11 +228,10 @@ struct LeanHeap {
   // Alg. 6: one free block [0, A).
   __device__ __forceinline__ void init() {
 #pragma unroll
-    for (int k = 0; k < RF; ++k) { fa[k] = kNone; fs[k] = 0u; fk[k] = 0u; }
-    F = 1; L = 0; rover = 0; clock = 1; cnt = 0;
+    for (int k = 0; k < RF; ++k) { fa[k] = kNone; fs[k] = 0u; fk[k] = kNone; }
+    F = 1; L = 0; rover = 0; clock = 1;
     set_room();
     write(0, 0u, ag, kSeg ? seg_key(ag) : 0u);
-    if (kSeg) cnt_add(byte_class(ag), 1);
   }
 
   // Remove free entry j: the last entry moves into its place and the last
@@ -302,19 +313,19 @@ struct LeanHeap {
       return true;
     } else {
       // segregated fit: the first non-empty class at or above the request's,
-      // and in it the block pushed last (Alg. 4)
+      // and in it the block pushed last (Alg. 4): the smallest key at or
+      // above the request's class
       if (kreq >= 64u) return false;
-      const uint64_t bm = ballot(cnt != 0u) & (~0ull << kreq);
-      if (bm == 0ull) return false;
-      const uint32_t c = ctz64(bm);
-      const uint32_t lim = c >= 63u ? kNone : (c + 1u) << kKeyShift;
-      uint32_t best = 0u, bc = 0;
+      const uint32_t lo = kreq << kKeyShift;
+      uint32_t best = kNone, bc = 0;
       scan([&](uint32_t ch, uint32_t, uint32_t, uint32_t ek) {
-        const bool take = ek < lim && ek > best;
-        best = take ? ek : best;
-        bc = take ? ch : bc;
+        const uint32_t t = ek >= lo ? ek : kNone;
+        const bool lt = t < best;
+        best = lt ? t : best;
+        bc = lt ? ch : bc;
       });
-      const uint32_t K = wave_max(best);
+      const uint32_t K = wave_min(best);
+      if (K == kNone) return false;
       const uint32_t l = ctz64(ballot(best == K));
       j = 64u * rdlane(bc, l) + l;
       uint32_t k;
@@ -333,10 +344,8 @@ struct LeanHeap {
     if (s > sg) {  // Alg. 1 / Alg. 4: the block is cut from the low end
       if (kSeg && clock >= kStampLimit) return kOverflow;
       write(j, a + sg, s - sg, kSeg ? seg_key(s - sg) : 0u);
-      if (kSeg) { cnt_add(byte_class(s), -1); cnt_add(byte_class(s - sg), 1); }
     } else {
       remove(j);
-      if (kSeg) cnt_add(byte_class(s), -1);
     }
     live_write(L, a, sg);
     ++L;
@@ -367,22 +376,19 @@ struct LeanHeap {
       if (need_bytes(F + 1u, L) > m.bytes) return kOverflow;
       if (F >= HF && ((F - HF) & 63u) == 0u) {  // a new LDS chunk: its slots start empty
         wave_sync();
-        cold_put(F - HF + lane_id(), kNone, 0u, 0u);
+        cold_put(F - HF + lane_id(), kNone, 0u, kNone);
       }
       write(F, x, sz, kSeg ? seg_key(sz) : 0u);
-      if (kSeg) cnt_add(byte_class(sz), 1);
       ++F;
       set_room();
     } else if (MR == 0ull) {
       const uint32_t l = ctz64(ML), jl = 64u * rdlane(cl, l) + l;
       const uint32_t sl = size_at(jl);
       write(jl, x - sl, sl + sz, kSeg ? seg_key(sl + sz) : 0u);
-      if (kSeg) { cnt_add(byte_class(sl), -1); cnt_add(byte_class(sl + sz), 1); }
     } else if (ML == 0ull) {
       const uint32_t l = ctz64(MR), jr = 64u * rdlane(cr, l) + l;
       const uint32_t sr = size_at(jr);
       write(jr, x, sz + sr, kSeg ? seg_key(sz + sr) : 0u);
-      if (kSeg) { cnt_add(byte_class(sr), -1); cnt_add(byte_class(sz + sr), 1); }
     } else {
       const uint32_t ll = ctz64(ML), jl = 64u * rdlane(cl, ll) + ll;
       const uint32_t lr = ctz64(MR), jr = 64u * rdlane(cr, lr) + lr;
@@ -401,11 +407,6 @@ struct LeanHeap {
       }
       write(keep, x - sl, ms, kSeg ? seg_key(ms) : 0u);
       clear(last);
-      if (kSeg) {
-        cnt_add(byte_class(sl), -1);
-        cnt_add(byte_class(sr), -1);
-        cnt_add(byte_class(ms), 1);
-      }
       F = last;
       set_room();
     }
@@ -431,6 +432,7 @@ struct LeanHeap {
   // beside it, every live entry i to device slot i.
   __device__ void migrate(const Cold& c, HeapRegs& h) {
     const uint32_t lane = lane_id();
+    const uint32_t counts = kSeg ? class_counts() : 0u;
     for (uint32_t ch = RF; 64u * ch < F; ++ch) {
       const uint32_t gi = 64u * ch + lane;
       wave_sync();
@@ -438,7 +440,7 @@ struct LeanHeap {
       cold_get(64u * (ch - RF) + lane, a, s, k);
       if (gi < F) {
         c.gf[gi] = mk_ent(a, s);
-        if (kSeg) c.gst[gi] = k & (kStampLimit - 1u);
+        if (kSeg) c.gst[gi] = (k & kStampMask) ^ kStampMask;
       }
     }
 #pragma unroll
@@ -446,7 +448,7 @@ struct LeanHeap {
       const uint32_t gi = 64u * (uint32_t)k + lane;
       if (gi < F) {
         c.gf[gi] = mk_ent(fa[k], fs[k]);
-        if (kSeg) c.gst[gi] = fk[k] & (kStampLimit - 1u);
+        if (kSeg) c.gst[gi] = (fk[k] & kStampMask) ^ kStampMask;
       }
     }
     for (uint32_t base = 0; base < L; base += 64u) {
@@ -460,7 +462,7 @@ struct LeanHeap {
     h.L = L;
     h.rover = rover;
     h.clock = clock;
-    h.cnt = cnt;
+    h.cnt = counts;
   }
 
   // Canonical state, same format as the general core (hda.h).
@@ -497,6 +499,7 @@ struct LeanHeap {
       }
     }
     int64_t* tail = lo + 1 + 2 * (int64_t)L;
+    const uint32_t cnt = kSeg ? class_counts() : 0u;
     const uint64_t bm = ballot(cnt != 0u);
     if (lane == 0) {
       tail[0] = ALGO == kNextFit ? (int64_t)((uint64_t)rover << sh) : -1;
@@ -512,7 +515,7 @@ struct LeanHeap {
         acc += 1u + rdlane(cnt, k);
       }
       if (hdr < region) ls[hdr] = cnt;
-      // within a class, blocks from the last pushed (largest key) down
+      // within a class, blocks from the last pushed (smallest key) on
       scan([&](uint32_t c, uint32_t a, uint32_t, uint32_t key) {
         const bool v = 64u * c + lane < F;
         const uint32_t cls = v ? key >> kKeyShift : 0u;
@@ -520,7 +523,7 @@ struct LeanHeap {
         for (uint32_t j = 0; j < F; ++j) {
           uint32_t aj, sj, kj;
           read(j, aj, sj, kj);
-          rank += ((kj >> kKeyShift) == cls && kj > key) ? 1u : 0u;
+          rank += ((kj >> kKeyShift) == cls && kj < key) ? 1u : 0u;
         }
         const uint32_t hc = shfl(hdr, cls);
         if (v && hc + 1u + rank < region) ls[hc + 1u + rank] = (int64_t)((uint64_t)a << sh);
