@@ -327,8 +327,11 @@ struct WaveHeap {
         const bool take = v && s >= sg && a < k1;
         k1 = take ? a : k1; bi = take ? i : bi; bs = take ? s : bs;
       } else if constexpr (ALGO == kBestFit) {
-        const bool take = v && s >= sg && (s < k1 || (s == k1 && a < k2));
-        k1 = take ? s : k1; k2 = take ? a : k2; bi = take ? i : bi;
+        // keyed by the leftover s - sg (at most 2^32 - 2 since sg >= 1, so
+        // it never equals kNone, as a whole-arena size of 2^32 - 1 would)
+        const uint32_t d = s - sg;
+        const bool take = v && s >= sg && (d < k1 || (d == k1 && a < k2));
+        k1 = take ? d : k1; k2 = take ? a : k2; bi = take ? i : bi;
       } else if constexpr (ALGO == kNextFit) {
         const bool fit = v && s >= sg;
         const bool past = a + s > rover;
@@ -358,7 +361,7 @@ struct WaveHeap {
       }
       const uint32_t wl = ctz64(m);
       ja = rdlane(k2, wl);
-      js = K;
+      js = K + sg;
       return rdlane(bi, wl);
     } else {
       const uint32_t wl = ctz64(m);

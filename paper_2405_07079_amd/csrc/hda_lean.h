@@ -9,8 +9,9 @@
 //
 // Unused free slots hold address ~0 and size 0.  Such a slot never fits a
 // request (every request is at least one granule) and never borders a block
-// (no block starts or ends at granule ~0), so every scan covers whole chunks
-// with no bounds mask.
+// (no block starts at granule ~0; the one block that can end there, in an
+// arena of 2^32 - 1 granules, is matched by its start instead), so every
+// scan covers whole chunks with no bounds mask.
 //
 // When the tables would outgrow the pool before reaching the capacities the
 // caller asked for, the request stops with kOverflow (changing nothing), the
@@ -290,10 +291,12 @@ struct LeanHeap {
       a = ALGO == kFirstFit ? K : end - s;
       return true;
     } else if constexpr (ALGO == kBestFit) {
-      // smallest size, then lowest address
+      // smallest size, then lowest address; keyed by the leftover es - sg,
+      // which (sg >= 1) never equals kNone, as a whole-arena size of
+      // 2^32 - 1 granules would
       uint32_t bs = kNone, ba = kNone, bc = 0;
       scan([&](uint32_t c, uint32_t ea, uint32_t es, uint32_t) {
-        const uint32_t t = es >= sg ? es : kNone;
+        const uint32_t t = es >= sg ? es - sg : kNone;
         const bool take = t < bs || (t == bs && ea < ba);
         bs = take ? t : bs;
         ba = take ? ea : ba;
@@ -309,7 +312,7 @@ struct LeanHeap {
       const uint32_t l = ctz64(mk);
       j = 64u * rdlane(bc, l) + l;
       a = rdlane(ba, l);
-      s = K;
+      s = K + sg;
       return true;
     } else {
       // segregated fit: the first non-empty class at or above the request's,
@@ -358,9 +361,17 @@ struct LeanHeap {
   // place).  Returns the byte offset, kENoMeta or kOverflow.
   __device__ __forceinline__ int64_t free_index(uint32_t idx) {
     if (kSeg && clock >= kStampLimit) return kOverflow;
-    uint32_t x, sz;
+    // The victim and the last live entry (which takes the victim's slot at
+    // the end) are read together, so the second load's latency hides behind
+    // the first; nothing below writes the live table before that move.
+    const uint32_t lastL = L - 1u;
+    uint32_t x, sz, ta, ts;
     live_read(idx, x, sz);
-    const uint32_t xe = x + sz;
+    live_read(lastL, ta, ts);
+    // A block ending at granule ~0 (an arena of 2^32 - 1 granules) has no
+    // right neighbour; its own start, which no free block has, stands in for
+    // its end so that empty slots (address ~0) do not match.
+    const uint32_t xe = x + sz == kNone ? x : x + sz;
     uint64_t ML = 0ull, MR = 0ull;
     uint32_t cl = 0, cr = 0;
     scan([&](uint32_t c, uint32_t ea, uint32_t es, uint32_t) {
@@ -410,13 +421,8 @@ struct LeanHeap {
       F = last;
       set_room();
     }
-    const uint32_t last = L - 1u;
-    if (idx != last) {
-      uint32_t a, s;
-      live_read(last, a, s);
-      live_write(idx, a, s);
-    }
-    L = last;
+    live_write(idx, ta, ts);  // idx == lastL rewrites the entry about to be dropped
+    L = lastL;
     return (int64_t)((uint64_t)x << shift);
   }
 

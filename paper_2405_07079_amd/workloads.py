@@ -237,6 +237,34 @@ def random_tiny(seed: int, n: int, granules: int, align: int = 16,
                  np.array([0, n], np.int64), req, dict(seed=seed))
 
 
+def max_arena_batch(align: int = 64) -> Batch:
+    """Hand-written traces on the largest arena a heap may have, 2^32 - 1
+    granules: a block then ends at granule 2^32 - 1 and the whole free arena
+    has size 2^32 - 1.  Trace 0 fills the arena with two blocks, frees and
+    re-takes the one that ends there, then frees everything and asks for the
+    whole arena; trace 1 does the same with sizes segregated fit can serve
+    (the block ending at the arena end is exactly 2^31 granules).  Each trace
+    runs once per algorithm (heap 4 * trace + algorithm)."""
+    ag = (1 << 32) - 1
+    g = align
+    free = lambda r: -(r + 1)  # noqa: E731  (free with 32-bit draw r)
+    last_of_two, first = 0xC0000000, 0
+    t0 = [(1 << 31) * g, (ag - (1 << 31)) * g, free(last_of_two), 64, 128, free(first),
+          free(0xFFFFFFFF), 4096, free(0x80000000), free(first), ag * g, free(first),
+          ag * g, free(first)]
+    t1 = [((1 << 31) - 1) * g, (1 << 31) * g, free(last_of_two), (1 << 31) * g,
+          free(first), free(first), ag * g, 64, free(first), ((1 << 31) - 1) * g,
+          (1 << 31) * g, free(last_of_two), free(first)]
+    parts = []
+    for t in (t0, t1):
+        req = np.array(t, np.int64)
+        for algo in ALGO_NAMES:
+            parts.append(Batch("max_arena", np.array([ag * g], np.int64),
+                               np.array([g], np.int64), np.array([algo], np.int32),
+                               np.array([0, len(req)], np.int64), req))
+    return concat(parts, "max_arena")
+
+
 def concat(batches, name: str = "concat") -> Batch:
     """Concatenate batches heap-wise."""
     arena = np.concatenate([b.arena for b in batches])

@@ -170,3 +170,13 @@ def test_lean_invalid_heap_parameters():
     assert status.tolist() == [0, -2, 0]
     assert (res[b.req_off[1]:b.req_off[2]] == -2).all()
     check(b, res, states, status, heaps=[0, 2])
+
+
+def test_max_arena_edges():
+    """Arenas of 2^32 - 1 granules: a block can end at granule ~0 (the lean
+    core's empty-slot address) and the whole free arena's size equals the
+    32-bit "none" value.  General and lean cores, every algorithm."""
+    b = W.max_arena_batch()
+    for shape in (1, 3, 4):
+        res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=64, cl=64, shape=shape)
+        check(b, res, states, status)

@@ -34,6 +34,32 @@ def test_calls_match_oracle(algo):
     gh.close()
 
 
+@pytest.mark.parametrize("algo", (0, 1, 2, 3))
+def test_arena_of_2_32_minus_1_granules(algo):
+    """The largest arena a heap may have: the whole free arena's size and the
+    end of its last block are both 2^32 - 1 granules."""
+    print(f"case: 2^32 - 1 granule heap algo {algo}", flush=True)
+    g = 64
+    A = ((1 << 32) - 1) * g
+    gh = hda.Heap(A, g, algo, meta_cap=64)
+    oh = oracle.Heap(algo, A, g)
+    whole = gh.alloc(A)
+    assert whole == oh.alloc(A)
+    if whole >= 0:
+        assert gh.free(whole) == oh.free(whole) == 0
+    lo = gh.alloc(((1 << 31) - 1) * g)
+    hi = gh.alloc((1 << 31) * g)
+    assert (lo, hi) == (oh.alloc(((1 << 31) - 1) * g), oh.alloc((1 << 31) * g))
+    assert hi == ((1 << 31) - 1) * g   # ends at granule 2^32 - 1
+    assert gh.free(hi) == oh.free(hi) == 0
+    assert np.array_equal(gh.state(), oh.state())
+    assert gh.free(lo) == oh.free(lo) == 0
+    assert np.array_equal(gh.state(), oh.state())
+    assert gh.alloc(A) == oh.alloc(A)
+    assert np.array_equal(gh.state(), oh.state())
+    gh.close()
+
+
 @pytest.mark.parametrize("algo", (0, 3))
 def test_bad_and_double_free(algo):
     print(f"case: bad free algo {algo}", flush=True)

@@ -111,6 +111,17 @@ def test_spill_to_device_memory(algo, where):
     check_against_oracle(b, res, states, status)
 
 
+@pytest.mark.parametrize("where", ("default", "general_no_lds"))
+def test_max_arena_edges(where):
+    """Arenas of 2^32 - 1 granules (a block ending at granule ~0, a free
+    block of size 2^32 - 1) on the lean and the general core."""
+    b = W.max_arena_batch()
+    say(f"case: 2^32 - 1 granule arenas, {b.heaps} heaps, tables {where}")
+    tu = hda.tuning() if where == "default" else SPILL_TUNINGS[where]
+    res, states, status = gpu_replay(b, tuning=tu, meta_free=64, meta_live=64)
+    check_against_oracle(b, res, states, status)
+
+
 def test_tuning_does_not_change_results():
     b = W.concat([c2_like(16, 8000, a) for a in ALGOS], "mixed")
     ref = None
