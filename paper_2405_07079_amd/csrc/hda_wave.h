@@ -24,9 +24,11 @@ __device__ __forceinline__ uint32_t rdlane(uint32_t v, uint32_t l) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
 }
 
-// Lane l of v receives the wave-uniform value x; other lanes keep v.
+// Lane l of v receives the wave-uniform value x; other lanes keep v (one
+// v_writelane; l is taken mod 64).
+__device__ int hda_writelane(int x, int l, int v) __asm("llvm.amdgcn.writelane.i32");
 __device__ __forceinline__ uint32_t put_lane(uint32_t v, uint32_t l, uint32_t x) {
-  return lane_id() == l ? x : v;
+  return (uint32_t)hda_writelane((int)x, (int)l, (int)v);
 }
 
 // A value the optimiser may not trace back to the memory it was loaded
