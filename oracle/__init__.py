@@ -49,6 +49,8 @@ def lib():
         L.orc_alloc.argtypes = [vp, i64]
         L.orc_dealloc.restype = i32
         L.orc_dealloc.argtypes = [vp, i64]
+        L.orc_dealloc_partial.restype = i32
+        L.orc_dealloc_partial.argtypes = [vp, i64]
         L.orc_dump.restype = i64
         L.orc_dump.argtypes = [vp, vp, i64]
         L.orc_stats.argtypes = [vp, vp]
@@ -83,6 +85,11 @@ class Heap:
 
     def free(self, offset: int) -> int:
         return int(lib().orc_dealloc(self._h, int(offset)))
+
+    def free_partial(self, offset: int) -> int:
+        """Free from `offset` to the end of the live block holding it (the
+        whole block if `offset` is its start; sequential fits only)."""
+        return int(lib().orc_dealloc_partial(self._h, int(offset)))
 
     def replay(self, req) -> np.ndarray:
         req = np.ascontiguousarray(req, dtype=np.int64)

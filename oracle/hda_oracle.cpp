@@ -41,10 +41,21 @@
 //    floor(log2 size).  The null link is -1 (offset 0 is a valid address).
 //  * No allocation ever fails with an error: a request nothing can satisfy
 //    returns -1 and leaves the state (and the rover) unchanged.
-//  * Replay driver (not part of the paper): a free request carries a uniform
-//    32-bit draw r; the freed block is live[(r * L) >> 32] where live[] lists
-//    the live blocks (append on success, swap-with-last removal on free) and
-//    L = |live|.  With no live block the request does nothing and yields -1.
+//  * Partial deallocation (Sec. II-A, Alg. 2) is defined for the sequential
+//    fits only: freeing x inside the live block [b, b+s), b < x, shrinks it
+//    to [b, x) and releases [x, b+s) with the same merging as a whole block;
+//    the block keeps its place in live[].  x must be a multiple of g.
+//    Segregated fit frees exactly one keyed block (Alg. 5), so an interior
+//    address is a bad free there.
+//  * Replay driver (not part of the paper): a free request q < 0 carries
+//    u = ~q, a uniform 32-bit draw r = u mod 2^32 and a cut c = u >> 32
+//    (0 <= c < 2^31).  The victim is live[(r * L) >> 32] where live[] lists
+//    the live blocks (append on success, swap-with-last removal on a whole
+//    free) and L = |live|.  For the sequential fits the victim's first
+//    t = floor(c * (s / g) / 2^31) granules stay live and the rest is freed
+//    (t = 0: the whole block); segregated fit ignores c.  The result is the
+//    byte address freed.  With no live block the request does nothing and
+//    yields -1.
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
@@ -206,6 +217,22 @@ struct Heap {
         return 0;
     }
 
+    // Alg. 2 for an address that may lie inside a live block: the block
+    // holding x shrinks to end at x and the tail is released (sequential
+    // fits); x at a block's start frees the whole block.
+    int dealloc_partial(int64_t x) {
+        auto u = used.upper_bound(x);
+        if (u == used.begin()) return E_BADFREE;
+        --u;
+        int64_t b = u->first, s = u->second;
+        if (x >= b + s) return E_BADFREE;
+        if (x == b) return dealloc(x);
+        if (algo == SF || x % g != 0) return E_BADFREE;
+        u->second = x - b;           // it.size = addr - it.addr
+        dealloc_seq(x, b + s - x);   // size -= it.size
+        return 0;
+    }
+
     void dealloc_seq(int64_t x, int64_t s) {
         // Alg. 2: predecessor = last free block below x, successor = next.
         auto succ = fl.upper_bound(x);
@@ -301,11 +328,18 @@ void replay_one(Heap& h, int64_t n, const int64_t* req, int64_t* res) {
         } else if (h.live.empty()) {
             res[i] = -1;
         } else {
-            uint64_t r = uint32_t(~uint64_t(q));
+            uint64_t u = ~uint64_t(q);
+            uint64_t r = uint32_t(u), c = u >> 32;
             uint64_t idx = (r * uint64_t(h.live.size())) >> 32;
             int64_t x = h.live[idx];
-            h.dealloc(x);
-            res[i] = x;
+            int64_t keep = 0;        // bytes of the victim that stay live
+            if (h.algo != SF) keep = int64_t((c * uint64_t(h.used.at(x) / h.g)) >> 31) * h.g;
+            if (keep == 0) {
+                h.dealloc(x);
+            } else {
+                h.dealloc_partial(x + keep);
+            }
+            res[i] = x + keep;
         }
     }
 }
@@ -327,6 +361,9 @@ void* orc_heap_new(int algo, int64_t arena, int64_t align) {
 void orc_heap_delete(void* h) { delete static_cast<Heap*>(h); }
 int64_t orc_alloc(void* h, int64_t size) { return static_cast<Heap*>(h)->alloc(size); }
 int orc_dealloc(void* h, int64_t off) { return static_cast<Heap*>(h)->dealloc(off); }
+int orc_dealloc_partial(void* h, int64_t off) {
+    return static_cast<Heap*>(h)->dealloc_partial(off);
+}
 int64_t orc_dump(void* h, int64_t* buf, int64_t cap) {
     return copy_state(*static_cast<Heap*>(h), buf, cap);
 }

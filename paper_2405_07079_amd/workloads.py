@@ -93,10 +93,18 @@ def log_uniform_int(rng: np.random.Generator, n: int, lo: float, hi,
 
 
 def _stream(rng: np.random.Generator, n: int, p_alloc: float, sizes: np.ndarray,
-            ) -> np.ndarray:
-    """Mix allocation sizes with free draws: step i allocates w.p. p_alloc."""
+            p_partial: float = 0.0) -> np.ndarray:
+    """Mix allocation sizes with free draws: step i allocates w.p. p_alloc.
+    A free is encoded as -(u + 1) with u = cut << 32 | draw: a uniform 32-bit
+    draw picks the victim, and w.p. p_partial a cut uniform on [1, 2^31)
+    keeps that fraction of the victim live (partial deallocation; the cut is
+    0 otherwise, and no numbers are drawn for it when p_partial is 0)."""
     dec = rng.random(n)
     draw = rng.integers(0, 1 << 32, n, dtype=np.int64)
+    if p_partial > 0.0:
+        part = rng.random(n) < p_partial
+        cut = rng.integers(1, 1 << 31, n, dtype=np.int64)
+        draw = draw | np.where(part, cut, 0) << 32
     return np.where(dec < p_alloc, sizes, -(draw + 1)).astype(np.int64)
 
 
@@ -139,22 +147,22 @@ def uniform_batch(seed: int = 2, heaps: int = 4096, arena: int = 16 * MiB,
                   align: int = 64, n: int = 100_000, p_alloc: float = 0.55,
                   lo: int = 64, hi: int = 1 * MiB, algo: int = BEST_FIT,
                   name: str = "uniform_4096x16MiB", threads: int | None = None,
-                  ) -> Batch:
+                  p_partial: float = 0.0) -> Batch:
     """Many identical heaps (default: 4,096 heaps of 16 MiB at 64 B alignment,
     100,000 requests each, sizes log-uniform on [64 B, 1 MiB], alloc w.p.
-    0.55)."""
+    0.55).  p_partial > 0 makes that fraction of the frees partial."""
     lens = np.full(heaps, n, dtype=np.int64)
 
     def body(h, out):
         rng = heap_rng(seed, h)
         sizes = log_uniform_int(rng, n, lo, hi)
-        out[:] = _stream(rng, n, p_alloc, sizes)
+        out[:] = _stream(rng, n, p_alloc, sizes, p_partial)
 
     off, req = _fill_parallel(heaps, lens, body, threads)
     return Batch(name, np.full(heaps, arena, np.int64),
                  np.full(heaps, align, np.int64), np.full(heaps, algo, np.int32),
                  off, req, dict(seed=seed, p_alloc=p_alloc, size_lo=lo,
-                                size_hi=hi, steps=n))
+                                size_hi=hi, steps=n, p_partial=p_partial))
 
 
 def uneven_params(seed: int, heaps: int, arena_lo=1 * MiB, arena_hi=1 * GiB,
@@ -225,13 +233,13 @@ def large_seg_fit(seed: int = 5, n: int = 50_000_000, arena: int = 1 << 38,
 
 def random_tiny(seed: int, n: int, granules: int, align: int = 16,
                 p_alloc: float = 0.6, algo: int = FIRST_FIT,
-                max_granules: int | None = None) -> Batch:
+                max_granules: int | None = None, p_partial: float = 0.0) -> Batch:
     """A small heap of ``granules`` * ``align`` bytes with sizes uniform on
     [0, max_granules * align] bytes (0 included, to exercise the minimum)."""
     rng = heap_rng(seed, 0)
     mg = max_granules or max(1, granules // 2)
     sizes = rng.integers(0, mg * align + 1, n, dtype=np.int64)
-    req = _stream(rng, n, p_alloc, sizes)
+    req = _stream(rng, n, p_alloc, sizes, p_partial)
     return Batch("random_tiny", np.array([granules * align], np.int64),
                  np.array([align], np.int64), np.array([algo], np.int32),
                  np.array([0, n], np.int64), req, dict(seed=seed))

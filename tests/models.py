@@ -84,6 +84,24 @@ class BitmapHeap:
             self.bits[k] = True
         return 0
 
+    def free_partial(self, off: int) -> int:
+        """Free [off, end of the used block holding off): the used block keeps
+        its head (Sec. II-A); at the block's start this is a whole free."""
+        if off % self.g:
+            return -3
+        x = off // self.g
+        holder = [a for a, s in self.used.items() if a <= x < a + s]
+        if not holder:
+            return -3
+        a = holder[0]
+        if a == x:
+            return self.free(off)
+        end = a + self.used[a]
+        self.used[a] = x - a
+        for k in range(x, end):
+            self.bits[k] = True
+        return 0
+
     def state(self):
         g = self.g
         return dict(free=[(a * g, l * g) for a, l in runs(self.bits)],
@@ -153,6 +171,10 @@ class ListSegFit:
         self.lists[self.cls(size)].insert(0, start)
         return 0
 
+    def free_partial(self, off: int) -> int:
+        """Segregated fit frees whole keyed blocks only."""
+        return self.free(off)
+
     def state(self):
         sizes = {b[0]: b[1] for b in self.blocks}
         bitmap = 0
@@ -180,8 +202,21 @@ def draw_for(index: int, n_live: int) -> int:
     return -(r + 1)
 
 
+def draw_cut(q: int) -> int:
+    """The 31-bit cut of an encoded free request (0: free the whole block)."""
+    return (~q) >> 32
+
+
+def free_request(draw: int, cut: int = 0) -> int:
+    """Encode a free request from its 32-bit draw and 31-bit cut."""
+    assert 0 <= draw < (1 << 32) and 0 <= cut < (1 << 31)
+    return -((cut << 32 | draw) + 1)
+
+
 def replay(model, req):
-    """Replay an encoded trace on a model; returns the result list."""
+    """Replay an encoded trace on a model; returns the result list.  A free
+    keeps the victim's first floor(cut * granules / 2^31) granules live on
+    the sequential fits (none on segregated fit) and frees the rest."""
     out = []
     for q in req:
         q = int(q)
@@ -192,6 +227,13 @@ def replay(model, req):
         else:
             i = draw_index(q, len(model.live))
             off = model.live[i]
-            assert model.free(off) == 0
-            out.append(off)
+            keep = 0
+            if isinstance(model, BitmapHeap):
+                keep = (draw_cut(q) * model.used[off // model.g]) >> 31
+            if keep:
+                assert model.free_partial(off + keep * model.g) == 0
+                out.append(off + keep * model.g)
+            else:
+                assert model.free(off) == 0
+                out.append(off)
     return out

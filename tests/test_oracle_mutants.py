@@ -48,9 +48,19 @@ MUTANTS = [
      "uint64_t idx = r % uint64_t(h.live.size());", 0),
     ("driver_no_swap", "*lv = live.back();\n        live.pop_back();", "live.erase(lv);", 0),
     ("size_not_rounded", "int64_t s = (req + g - 1) / g * g;", "int64_t s = req;", 0),
+    # partial deallocation (Alg. 2)
+    ("partial_keeps_extra_granule", "u->second = x - b;", "u->second = x - b + g;", 0),
+    ("partial_frees_whole_size", "dealloc_seq(x, b + s - x);", "dealloc_seq(x, s);", 0),
+    ("partial_cut_scale", "h.g)) >> 31) * h.g;", "h.g)) >> 32) * h.g;", 0),
+    ("partial_result_is_block_start", "res[i] = x + keep;", "res[i] = x;", 0),
+    ("partial_unaligned_accepted", "if (algo == SF || x % g != 0) return E_BADFREE;",
+     "if (algo == SF) return E_BADFREE;", 0),
+    ("partial_on_seg_fit", "if (algo == SF || x % g != 0) return E_BADFREE;",
+     "if (x % g != 0) return E_BADFREE;", 0),
+    ("partial_cut_on_wrong_algos", "if (h.algo != SF) keep", "if (h.algo == SF) keep", 0),
 ]
 
-PINS = os.path.join(ROOT, "tests", "test_oracle_pins.py")
+PINS = [os.path.join(ROOT, "tests", f) for f in ("test_oracle_pins.py", "test_oracle_partial.py")]
 
 
 def _replace_nth(text, old, new, n):
@@ -73,7 +83,7 @@ def _run(m, tmp):
     subprocess.check_call(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-pthread",
                            cpp, "-o", so])
     env = dict(os.environ, HDA_ORACLE_LIB=so)
-    p = subprocess.run([sys.executable, "-m", "pytest", PINS, "-x", "-q",
+    p = subprocess.run([sys.executable, "-m", "pytest", *PINS, "-x", "-q",
                         "-p", "no:cacheprovider", "--timeout", "120",
                         "-k", "not depth6"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
