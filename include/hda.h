@@ -45,7 +45,8 @@ enum {
   HDA_OK = 0,
   HDA_FAIL = -1,      /* allocation: nothing fits (a result, not an error)   */
   HDA_E_INVAL = -2,   /* bad argument (see each function)                    */
-  HDA_E_BADFREE = -3, /* free of an offset that is not a live block's start  */
+  HDA_E_BADFREE = -3, /* free of an offset that is not a live block's start
+                          (partial free: that lies in no live block)         */
   HDA_E_NOMETA = -4,  /* per-heap metadata capacity exhausted                */
   HDA_E_DEVICE = -5,  /* a HIP runtime call failed                           */
   HDA_E_BUSY = -6,    /* resource in use (service running, budget held)      */
@@ -59,12 +60,18 @@ enum {
 /* Request encoding, one int64 per request, heap h owning
  * req[req_off[h] .. req_off[h+1]):
  *   req >= 0 : allocate req bytes;           result = byte offset, or -1.
- *   req <  0 : free one live block: r = (uint32_t)~req is a uniform 32-bit
- *              draw and the freed block is live[(r * L) >> 32], where live[]
- *              lists the heap's live blocks (a successful allocation appends
- *              its block; a free moves the last entry into the freed slot)
- *              and L is their number.  result = the freed offset, or -1 when
- *              no block is live (the request then does nothing).
+ *   req <  0 : free one live block: with u = ~req, r = u mod 2^32 is a
+ *              uniform 32-bit draw and the victim is live[(r * L) >> 32],
+ *              where live[] lists the heap's live blocks (a successful
+ *              allocation appends its block; a whole free moves the last
+ *              entry into the freed slot) and L is their number.  The cut
+ *              c = u >> 32 (< 2^31) asks for a partial deallocation (Sec.
+ *              II-A, Alg. 2; first, next and best fit): the victim's first
+ *              floor(c * granules / 2^31) granules stay live and the rest is
+ *              freed; 0 granules kept is a whole free.  Segregated fit
+ *              ignores c (Alg. 5 frees whole blocks).  result = the byte
+ *              offset of the freed part, or -1 when no block is live (the
+ *              request then does nothing).
  * A request that would exceed the heap's metadata capacity yields
  * HDA_E_NOMETA as its result and changes nothing.
  *
@@ -201,6 +208,15 @@ int64_t hda_alloc(hda_heap *h, uint64_t size);
  * (Alg. 2, Alg. 5).  HDA_E_BADFREE if `offset` is not the start of a live
  * block.  Synchronous. */
 int hda_free(hda_heap *h, int64_t offset);
+
+/* Partial deallocation (Sec. II-A, Alg. 2): free from `offset` to the end of
+ * the live block holding it.  The block keeps [start, offset) live; at the
+ * block's start this is hda_free.  HDA_E_BADFREE, state unchanged, if
+ * `offset` is not a multiple of the alignment or lies in no live block, and,
+ * for segregated fit (which frees whole keyed blocks, Alg. 5), if it is not
+ * a block's start.  HDA_E_NOMETA if the freed tail needs a table entry past
+ * the capacity.  Synchronous. */
+int hda_free_partial(hda_heap *h, int64_t offset);
 
 /* Copy the heap's canonical state (format above) into host buffer `buf` of
  * `cap` words; *len receives the words needed.  HDA_E_RANGE if cap < *len.

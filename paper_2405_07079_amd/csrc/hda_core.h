@@ -460,12 +460,18 @@ struct WaveHeap {
     return true;
   }
 
-  // Free the live block at live-table index idx.  Returns its byte offset or
-  // kENoMeta (state unchanged).
-  __device__ int64_t free_index(uint32_t idx) {
+  // Free the live block at live-table index idx except its first t granules
+  // (Alg. 2: t > 0 is a partial deallocation, the entry shrinks to t
+  // granules; t = 0 frees the whole block and drops the entry).  Returns the
+  // byte offset of the released part, or kENoMeta (state unchanged).
+  __device__ int64_t free_index(uint32_t idx, uint32_t t = 0u) {
     uint32_t x = 0, sz = 0;
     lread(idx, x, sz);
-    if (!release(x, sz)) return kENoMeta;
+    if (!release(x + t, sz - t)) return kENoMeta;
+    if (t != 0u) {
+      lwrite(idx, x, t);
+      return (int64_t)((uint64_t)(x + t) << h.shift);
+    }
     const uint32_t last = h.L - 1u;
     if (idx != last) {
       uint32_t a = 0, s = 0;
@@ -477,10 +483,18 @@ struct WaveHeap {
   }
 
   // Replay-driver free: r is the 32-bit draw, the victim is
-  // live[(r * L) >> 32]; nothing live -> -1.
-  __device__ __forceinline__ int64_t free_draw(uint32_t r) {
+  // live[(r * L) >> 32]; the sequential fits keep its first
+  // floor(cut * size / 2^31) granules (cut < 2^31); nothing live -> -1.
+  __device__ __forceinline__ int64_t free_draw(uint32_t r, uint32_t cut = 0u) {
     if (h.L == 0u) return kFail;
-    return free_index((uint32_t)(((uint64_t)r * (uint64_t)h.L) >> 32));
+    const uint32_t idx = (uint32_t)(((uint64_t)r * (uint64_t)h.L) >> 32);
+    uint32_t t = 0u;
+    if (!kSeg && cut != 0u) {
+      uint32_t x = 0, sz = 0;
+      lread(idx, x, sz);
+      t = (uint32_t)(((uint64_t)cut * sz) >> 31);
+    }
+    return free_index(idx, t);
   }
 
   // Free by byte offset (the call-by-call interface): find the live entry.
@@ -497,6 +511,31 @@ struct WaveHeap {
     }
     if (idx == kNone) return kEBadFree;
     const int64_t r = free_index(idx);
+    return r < 0 ? r : 0;
+  }
+
+  // Partial free by byte offset (the call-by-call interface, Alg. 2): the
+  // live block holding the offset keeps the part below it and the rest is
+  // released; at a block's start this is a whole free.  Segregated fit frees
+  // whole blocks only (Alg. 5): an interior offset is a bad free there.
+  __device__ int64_t free_partial(int64_t off) {
+    const uint64_t gm = (1ull << h.shift) - 1ull;
+    if (off < 0 || off >= h.arena || ((uint64_t)off & gm)) return kEBadFree;
+    const uint32_t x = (uint32_t)((uint64_t)off >> h.shift);
+    uint32_t idx = kNone, t = 0u;
+    for (uint32_t base = 0; base < h.L && idx == kNone; base += 64u) {
+      uint32_t a = 0, s = 0;
+      lchunk_any(base, a, s);
+      // x - a < s (unsigned) holds exactly for a <= x < a + s
+      const uint64_t m = ballot(base + lane_id() < h.L && x - a < s);
+      if (m) {
+        const uint32_t w = ctz64(m);
+        idx = base + w;
+        t = x - rdlane(a, w);
+      }
+    }
+    if (idx == kNone || (kSeg && t != 0u)) return kEBadFree;
+    const int64_t r = free_index(idx, t);
     return r < 0 ? r : 0;
   }
 

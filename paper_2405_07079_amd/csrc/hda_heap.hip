@@ -19,7 +19,7 @@ using namespace hda;
 
 namespace {
 
-enum : int { kOpInit = 0, kOpAlloc = 1, kOpFree = 2, kOpDump = 3 };
+enum : int { kOpInit = 0, kOpAlloc = 1, kOpFree = 2, kOpDump = 3, kOpFreePartial = 4 };
 
 template <int ALGO>
 __device__ void heap_call_t(HeapHdr* hd, int op, int64_t arg, int64_t* out, int64_t cap) {
@@ -32,6 +32,8 @@ __device__ void heap_call_t(HeapHdr* hd, int op, int64_t arg, int64_t* out, int6
     r = arg < 0 ? kEInval : w.alloc_bytes(arg);
   } else if (op == kOpFree) {
     r = w.free_offset(arg);
+  } else if (op == kOpFreePartial) {
+    r = w.free_partial(arg);
   } else {
     r = w.dump(out + 1, cap - 1);
   }
@@ -166,6 +168,13 @@ int hda_free(hda_heap* h, int64_t offset) {
   return rc != HDA_OK ? rc : (int)r;
 }
 
+int hda_free_partial(hda_heap* h, int64_t offset) {
+  if (!h) return HDA_E_INVAL;
+  int64_t r = 0;
+  const int rc = call(h, kOpFreePartial, offset, &r, nullptr, 0, nullptr);
+  return rc != HDA_OK ? rc : (int)r;
+}
+
 int hda_heap_state(const hda_heap* h, int64_t* buf, size_t cap, size_t* len) {
   if (!h || !len || (cap && !buf)) return HDA_E_INVAL;
   return call(const_cast<hda_heap*>(h), kOpDump, 0, nullptr, buf, cap, len);
@@ -181,7 +190,8 @@ const char* hda_strerror(int code) {
     case HDA_OK: return "ok";
     case HDA_FAIL: return "allocation failed: no free block fits";
     case HDA_E_INVAL: return "invalid argument";
-    case HDA_E_BADFREE: return "free of an offset that is not a live block's start";
+    case HDA_E_BADFREE:
+      return "free of an offset that is not a live block's start (partial free: in no live block)";
     case HDA_E_NOMETA: return "metadata capacity or budget exhausted";
     case HDA_E_DEVICE: return "HIP runtime error";
     case HDA_E_BUSY: return "resource busy";

@@ -356,18 +356,23 @@ struct LeanHeap {
     return (int64_t)((uint64_t)a << shift);
   }
 
-  // Free live entry idx: coalesce with free neighbours (Alg. 2 / Alg. 5),
-  // then drop the entry from the live table (the last one moves into its
-  // place).  Returns the byte offset, kENoMeta or kOverflow.
-  __device__ __forceinline__ int64_t free_index(uint32_t idx) {
+  // Free live entry idx except its first floor(cut * size / 2^31) granules
+  // (partial deallocation, sequential fits only; cut < 2^31): coalesce the
+  // released part with free neighbours (Alg. 2 / Alg. 5), then shrink the
+  // entry or, for a whole free, drop it from the live table (the last one
+  // moves into its place).  Returns the byte offset of the released part,
+  // kENoMeta or kOverflow.
+  __device__ __forceinline__ int64_t free_index(uint32_t idx, uint32_t cut) {
     if (kSeg && clock >= kStampLimit) return kOverflow;
     // The victim and the last live entry (which takes the victim's slot at
     // the end) are read together, so the second load's latency hides behind
     // the first; nothing below writes the live table before that move.
     const uint32_t lastL = L - 1u;
-    uint32_t x, sz, ta, ts;
-    live_read(idx, x, sz);
+    uint32_t bx, bsz, ta, ts;
+    live_read(idx, bx, bsz);
     live_read(lastL, ta, ts);
+    const uint32_t t = (kSeg || cut == 0u) ? 0u : (uint32_t)(((uint64_t)cut * bsz) >> 31);
+    const uint32_t x = bx + t, sz = bsz - t;  // the part released
     // A block ending at granule ~0 (an arena of 2^32 - 1 granules) has no
     // right neighbour; its own start, which no free block has, stands in for
     // its end so that empty slots (address ~0) do not match.
@@ -421,16 +426,20 @@ struct LeanHeap {
       F = last;
       set_room();
     }
-    live_write(idx, ta, ts);  // idx == lastL rewrites the entry about to be dropped
-    L = lastL;
+    if (t != 0u) {
+      live_write(idx, bx, t);
+    } else {
+      live_write(idx, ta, ts);  // idx == lastL rewrites the entry about to be dropped
+      L = lastL;
+    }
     return (int64_t)((uint64_t)x << shift);
   }
 
   // Replay free: r is the 32-bit draw, the victim is live[(r * L) >> 32];
-  // nothing live -> -1.
-  __device__ __forceinline__ int64_t free_draw(uint32_t r) {
+  // cut as in free_index; nothing live -> -1.
+  __device__ __forceinline__ int64_t free_draw(uint32_t r, uint32_t cut) {
     if (L == 0u) return kFail;
-    return free_index((uint32_t)(((uint64_t)r * (uint64_t)L) >> 32));
+    return free_index((uint32_t)(((uint64_t)r * (uint64_t)L) >> 32), cut);
   }
 
   // Hand this heap over to the general core (hda_core.h) on tiers `c` with

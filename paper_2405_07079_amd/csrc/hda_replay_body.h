@@ -54,10 +54,41 @@ __device__ __forceinline__ bool heap_params(const ReplayParams& p, int64_t heap,
   return true;
 }
 
+// Requests j < n of one block of 64 on core w: lane j of w0 holds request
+// j's draw (free) or size in granules (allocation, 0 = larger than the
+// arena), lane j of w1 its byte class (segregated fit) or its cut (free,
+// other fits; read only when CUT), bit j of mfree marks the frees.  Results
+// go to lane j of olo / ohi.  Returns the number of requests run: n, or the
+// index of the request that found the lean core's tiers too small.
+template <int ALGO, bool CUT, typename Core>
+__device__ __forceinline__ uint32_t run_block(Core& w, uint32_t n, uint32_t w0, uint32_t w1,
+                                              uint64_t mfree, uint32_t& olo, uint32_t& ohi,
+                                              int32_t& st) {
+  uint32_t done = n;
+  for (uint32_t j = 0; j < n; ++j) {
+    const uint32_t v0 = rdlane(w0, j);
+    int64_t r;
+    if ((mfree >> j) & 1ull) {
+      r = w.free_draw(v0, CUT ? rdlane(w1, j) : 0u);
+    } else if (v0 == 0u) {
+      r = kFail;
+    } else {
+      r = w.alloc(v0, ALGO == kSegFit ? rdlane(w1, j) : 0u);
+    }
+    if (r == kOverflow) { done = j; break; }
+    if (r == kENoMeta && st == 0) st = (int32_t)kENoMeta;
+    olo = put_lane(olo, j, (uint32_t)(uint64_t)r);
+    ohi = put_lane(ohi, j, (uint32_t)((uint64_t)r >> 32));
+  }
+  return done;
+}
+
 // Run requests [from, to) of `heap` on core w (either core type).  Requests
 // are read 64 at a time (one per lane) and decoded by all lanes at once: a
-// free carries its draw, an allocation its size in granules (0 when larger
-// than the arena) and, for segregated fit, its byte class.  Loads are clamped
+// free carries its draw and, for the sequential fits, its cut (the fraction
+// of the victim kept live, partial deallocation), an allocation its size in
+// granules (0 when larger than the arena) and, for segregated fit, its byte
+// class.  Loads are clamped
 // to the heap's last request instead of guarded by a lane-dependent branch,
 // since the values feed wave-wide reads.  Returns the position of the first
 // request not run: `to`, or the request that found the lean core's tiers too
@@ -77,26 +108,18 @@ __device__ int64_t run_requests(const ReplayParams& p, Core& w, int64_t from, in
     uint32_t sg = (uint32_t)(((uint64_t)q + gm) >> shift);
     sg = sg == 0u ? 1u : sg;
     const uint32_t w0 = is_free ? (uint32_t)~(uint64_t)q : (big ? 0u : sg);
-    const uint32_t w1 = ceil_log2_u32(sg) + shift;
+    // segregated fit: the byte class; the other fits: a free's cut
+    const uint32_t w1 = ALGO == kSegFit ? ceil_log2_u32(sg) + shift
+                                        : (is_free ? (uint32_t)(~(uint64_t)q >> 32) : 0u);
     const uint64_t mfree = ballot(is_free);
     const uint32_t n = (uint32_t)min<int64_t>(64, to - base);
     uint32_t olo = 0, ohi = 0;
-    uint32_t done = n;
-    for (uint32_t j = 0; j < n; ++j) {
-      const uint32_t v0 = rdlane(w0, j);
-      int64_t r;
-      if ((mfree >> j) & 1ull) {
-        r = w.free_draw(v0);
-      } else if (v0 == 0u) {
-        r = kFail;
-      } else {
-        r = w.alloc(v0, ALGO == kSegFit ? rdlane(w1, j) : 0u);
-      }
-      if (r == kOverflow) { done = j; break; }
-      if (r == kENoMeta && st == 0) st = (int32_t)kENoMeta;
-      olo = put_lane(olo, j, (uint32_t)(uint64_t)r);
-      ohi = put_lane(ohi, j, (uint32_t)((uint64_t)r >> 32));
-    }
+    // a block whose frees carry no cut runs a copy with the partial-free
+    // logic folded away
+    const uint32_t done =
+        (ALGO != kSegFit && ballot(is_free && w1 != 0u) != 0ull)
+            ? run_block<ALGO, ALGO != kSegFit>(w, n, w0, w1, mfree, olo, ohi, st)
+            : run_block<ALGO, false>(w, n, w0, w1, mfree, olo, ohi, st);
     if (lane < done) p.res[base + lane] = (int64_t)(((uint64_t)ohi << 32) | olo);
     if (done < n) return base + done;
   }

@@ -97,7 +97,7 @@ _lib = None
 EXPORTS = ["hda_replay_workspace", "hda_replay_resolve", "hda_replay",
            "hda_replay_per_heap", "hda_replay_autotune", "hda_replay_capture",
            "hda_graph_launch", "hda_graph_destroy", "hda_heap_create", "hda_heap_destroy", "hda_alloc",
-           "hda_free", "hda_heap_state", "hda_set_meta_budget", "hda_strerror",
+           "hda_free", "hda_free_partial", "hda_heap_state", "hda_set_meta_budget", "hda_strerror",
            "hda_serve_start", "hda_serve_open", "hda_serve_submit", "hda_serve_poll",
            "hda_serve_wait", "hda_serve_close", "hda_serve_stop", "hda_serve_load"]
 
@@ -137,6 +137,8 @@ def lib():
         L.hda_alloc.argtypes = [vp, ctypes.c_uint64]
         L.hda_free.restype = ctypes.c_int
         L.hda_free.argtypes = [vp, ctypes.c_int64]
+        L.hda_free_partial.restype = ctypes.c_int
+        L.hda_free_partial.argtypes = [vp, ctypes.c_int64]
         L.hda_heap_state.restype = ctypes.c_int
         L.hda_heap_state.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
         L.hda_set_meta_budget.restype = ctypes.c_int64
@@ -388,6 +390,9 @@ class Heap:
 
     def free(self, offset: int) -> int:
         return int(lib().hda_free(self._h, int(offset)))
+
+    def free_partial(self, offset: int) -> int:
+        return int(lib().hda_free_partial(self._h, int(offset)))
 
     def state(self) -> np.ndarray:
         n = ctypes.c_size_t(0)

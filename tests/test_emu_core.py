@@ -180,3 +180,45 @@ def test_max_arena_edges():
     for shape in (1, 3, 4):
         res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=64, cl=64, shape=shape)
         check(b, res, states, status)
+
+
+# ---- partial deallocation (the sequential fits keep a head of the victim;
+# segregated fit ignores the cut) ----
+
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("shape", (1, 3, 4))
+def test_partial_frees_16MiB_heap(algo, shape):
+    b = W.uniform_batch(heaps=1, n=2500, algo=algo, p_partial=0.5)
+    ovf = np.zeros(b.heaps, np.uint8)
+    res, states, status, _ = emu.replay(b, kf=512, kl=1024, cf=4096, cl=4096, shape=shape,
+                                        overflowed=ovf)
+    check(b, res, states, status)
+    assert not ovf.any()
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_partial_frees_lean_overflow(algo):
+    """Tiers too small: the heap moves to the general core mid-trace with
+    shrunk live entries in its tables."""
+    b = W.uniform_batch(heaps=1, n=2000, algo=algo, p_partial=0.5)
+    ovf = np.zeros(b.heaps, np.uint8)
+    res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=4096, cl=4096, shape=3,
+                                        overflowed=ovf)
+    check(b, res, states, status)
+    assert ovf.all()
+
+
+def test_partial_frees_random_small_heaps():
+    rng = np.random.default_rng(12)
+    parts = []
+    for h in range(40):
+        gran = int(rng.integers(1, 400))
+        parts.append(W.random_tiny(int(rng.integers(1 << 30)), int(rng.integers(0, 400)),
+                                   gran, align=int(1 << rng.integers(0, 12)),
+                                   algo=int(rng.integers(0, 4)),
+                                   max_granules=max(1, gran // int(rng.integers(1, 8))),
+                                   p_partial=float(rng.uniform(0.1, 1.0))))
+    b = W.concat(parts)
+    for shape in (1, 3):
+        res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=512, cl=512, shape=shape)
+        check(b, res, states, status)

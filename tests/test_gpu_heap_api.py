@@ -60,6 +60,38 @@ def test_arena_of_2_32_minus_1_granules(algo):
     gh.close()
 
 
+@pytest.mark.parametrize("algo", (0, 1, 2, 3))
+def test_partial_free_calls_match_oracle(algo):
+    """hda_free_partial at random offsets (block starts, interior granule
+    boundaries, unaligned, free space) against the oracle's partial free."""
+    print(f"case: call-by-call partial frees algo {algo}", flush=True)
+    A, g = 1 << 16, 32
+    gh = hda.Heap(A, g, algo, meta_cap=512)
+    oh = oracle.Heap(algo, A, g)
+    rng = np.random.default_rng(40 + algo)
+    live = {}
+    for step in range(300):
+        if live and rng.random() < 0.5:
+            a = int(rng.choice(sorted(live)))
+            kind = rng.integers(4)
+            off = (a if kind == 0 else a + g * int(rng.integers(0, live[a] // g)) if kind == 1
+                   else a + 1 if kind == 2 else int(rng.integers(0, A // g)) * g)
+            r = gh.free_partial(off)
+            assert r == oh.free_partial(off), (step, off)
+            if r == 0:
+                live = {x: s for x, s in oracle.parse_state(oh.state(), algo)["live"]}
+        else:
+            size = int(rng.integers(1, 3000))
+            r = gh.alloc(size)
+            assert r == oh.alloc(size), step
+            if r >= 0:
+                live = {x: s for x, s in oracle.parse_state(oh.state(), algo)["live"]}
+        if step % 50 == 0:
+            assert np.array_equal(gh.state(), oh.state())
+    assert np.array_equal(gh.state(), oh.state())
+    gh.close()
+
+
 @pytest.mark.parametrize("algo", (0, 3))
 def test_bad_and_double_free(algo):
     print(f"case: bad free algo {algo}", flush=True)

@@ -122,6 +122,20 @@ def test_max_arena_edges(where):
     check_against_oracle(b, res, states, status)
 
 
+@pytest.mark.parametrize("algo", ALGOS)
+@pytest.mark.parametrize("where", ("default", "lean_overflow", "general_lds64"))
+def test_partial_frees(algo, where):
+    """Half the frees are partial (the victim keeps a head; segregated fit
+    ignores the cut), on the lean core, through the move to the general core,
+    and on the general core alone."""
+    b = W.uniform_batch(seed=6, heaps=24, n=20_000, algo=algo, p_partial=0.5)
+    say(f"case: 24 x 16 MiB heaps, 20k requests, half the frees partial, algo {algo}, "
+        f"tables {where}")
+    tu = hda.tuning() if where == "default" else SPILL_TUNINGS[where]
+    res, states, status = gpu_replay(b, tuning=tu)
+    check_against_oracle(b, res, states, status)
+
+
 def test_tuning_does_not_change_results():
     b = W.concat([c2_like(16, 8000, a) for a in ALGOS], "mixed")
     ref = None
