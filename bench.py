@@ -117,6 +117,9 @@ def main():
     ap.add_argument("--tuning", type=str, default="0,0,0,0,0,0",
                     help="heaps_per_group,reg_free,reg_live,lds_free,lds_live,groups "
                          "(0 = default, -1 = none)")
+    ap.add_argument("--partial-frees", type=float, default=0.02,
+                    help="fraction of frees that are partial (Alg. 2) in the partial-"
+                         "deallocation leg, a best-fit batch of the same shape (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (a kernel of "
                          "known traffic for scaling memory counters)")
@@ -214,6 +217,37 @@ def main():
     per_heap_value = ph_ops / ph_time
     log(f"[bench] per-heap launches: {per_heap_value / 1e6:.2f} M ops/s on {S} heaps/algo")
 
+    partial = None
+    if args.partial_frees > 0:
+        # the same batch shape on best fit, with that fraction of the frees
+        # partial: the victim keeps a uniform fraction of its granules
+        pb = W.uniform_batch(heaps=args.heaps, n=args.requests, algo=W.BEST_FIT,
+                             p_partial=args.partial_frees)
+        pdb = hda.upload(pb, tuning=tuning)
+        hda.hda_replay(pdb, stream)
+        torch.cuda.synchronize()
+        if int((pdb.status != 0).sum().item()):
+            raise RuntimeError("partial-free leg: heaps reported errors")
+        pms = []
+        for _ in range(max(1, args.steps)):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            hda.hda_replay(pdb, stream)
+            e1.record(stream)
+            pms.append((e0, e1))
+        torch.cuda.synchronize()
+        pms = [a.elapsed_time(b) for a, b in pms]
+        n_partial = int((pb.req < -(1 << 32)).sum())
+        partial = {"workload": f"{pb.heaps} heaps x 16 MiB, {args.requests} requests each, "
+                               f"best fit, {args.partial_frees:g} of the frees partial",
+                   "value": pb.requests / (float(np.median(pms)) / 1e3), "unit": "ops/s",
+                   "launch_ms": float(np.median(pms)), "partial_frees": n_partial,
+                   "frees": int((pb.req < 0).sum())}
+        del pdb
+        log(f"[bench] partial frees ({args.partial_frees:g}): "
+            f"{partial['value'] / 1e9:.3f} G ops/s")
+
     serving = None
     if args.serve_rate > 0:
         # device-resident service: one heap per client (64 MiB-4 GiB, 512 B
@@ -259,6 +293,15 @@ def main():
                          f"{csub.requests * len(algos)} requests, {ct:.1f} s wall "
                          f"on {cores} threads"}
         log(f"[bench] cpu oracle: {cpu['value'] / 1e6:.2f} M ops/s on {cores} threads")
+        if partial is not None:
+            psub = pb.subset(np.arange(min(256, pb.heaps)))
+            t1 = time.perf_counter()
+            oracle.replay_batch(psub, threads=cores, want_state=True)
+            pt = time.perf_counter() - t1
+            partial["cpu_baseline"] = {"value": psub.requests / pt, "unit": "ops/s",
+                                       "cores": cores, "kind": "oracle",
+                                       "sample": f"first {psub.heaps} heaps, {psub.requests} "
+                                                 f"requests, {pt:.1f} s wall"}
 
     traffic = recorded_traffic([W.ALGO_NAMES[a] for a in algos])
     out = {
@@ -301,6 +344,7 @@ def main():
                      "avg_launch_ms": avg_launch_s * 1e3,
                      "bytes_per_request": BYTES_PER_REQUEST,
                      "requests_per_launch": batch.requests},
+        "partial_free": partial,
         "serving": serving,
         "cpu_baseline": cpu,
     }

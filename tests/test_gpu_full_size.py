@@ -5,6 +5,7 @@ on properties that hold at any size).
 * 4,096 heaps x 100,000 requests (16 MiB arenas), best fit and segregated
   fit, default tuning, states dumped: 24 sampled heaps per algorithm
   (including the first and the last) compared element by element.
+* The same batch on best fit with 2 % of the frees partial: 24 sampled heaps.
 * The uneven batch (16,384 heaps, 46.9 M requests), autotuned and launched
   as a captured graph: 48 sampled heaps plus the 4 longest.
 * The service under 1e7 requests/s from 100,000 clients (one heap each):
@@ -59,6 +60,25 @@ def test_4096_heaps_full_size_sampled(c2, algo):
     heaps = sorted(set(rng.choice(b.heaps, 22, replace=False).tolist()) | {0, b.heaps - 1})
     res = np.empty(b.requests, np.int64)
     for h in heaps:   # copy only the sampled heaps' results back
+        a, e = int(b.req_off[h]), int(b.req_off[h + 1])
+        res[a:e] = db.res[a:e].cpu().numpy()
+    check_heaps(b, res, db, status, heaps)
+
+
+def test_4096_heaps_partial_frees_full_size_sampled():
+    """The benchmark's partial-deallocation leg: best fit, 2 % of the frees
+    partial, default tuning; 24 sampled heaps element by element."""
+    b = W.uniform_batch(algo=W.BEST_FIT, p_partial=0.02)
+    say("case: 4096 x 16 MiB heaps, 100k requests each, best fit, 2 % partial frees")
+    db = hda.upload(b)
+    hda.hda_replay(db)
+    torch.cuda.synchronize()
+    status = db.status.cpu().numpy()
+    assert (status == 0).all()
+    rng = np.random.default_rng(77)
+    heaps = sorted(set(rng.choice(b.heaps, 22, replace=False).tolist()) | {0, b.heaps - 1})
+    res = np.empty(b.requests, np.int64)
+    for h in heaps:
         a, e = int(b.req_off[h]), int(b.req_off[h + 1])
         res[a:e] = db.res[a:e].cpu().numpy()
     check_heaps(b, res, db, status, heaps)
