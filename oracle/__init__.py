@@ -16,7 +16,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "hda_oracle.cpp")
 LIB = os.path.join(HERE, "libhda_oracle.so")
 
-FIRST_FIT, NEXT_FIT, BEST_FIT, SEG_FIT = 0, 1, 2, 3
+FIRST_FIT, NEXT_FIT, BEST_FIT, SEG_FIT, TLSF = 0, 1, 2, 3, 4
+
+
+def n_lists(algo: int) -> int:
+    """Class lists in a state dump: 64 (segregated fit), 64 * 32 (TLSF), 0."""
+    return 64 if algo == SEG_FIT else 64 * 32 if algo == TLSF else 0
 E_INVAL, E_BADFREE = -2, -3
 
 _lib = None
@@ -119,7 +124,7 @@ def replay_heap(algo, arena, align, req):
 def state_capacity(algo: int, n_requests: int, cap_blocks: int | None = None):
     """Words needed for a state dump when at most ``cap_blocks`` blocks exist."""
     b = n_requests + 1 if cap_blocks is None else cap_blocks
-    return 4 + 4 * b + (64 + b if algo == SEG_FIT else 0)
+    return 4 + 4 * b + (n_lists(algo) + b if n_lists(algo) else 0)
 
 
 def replay_batch(batch, threads: int = 1, want_state: bool = True,
@@ -168,9 +173,9 @@ def parse_state(st, algo: int):
     live = [(st[p + 2 * i], st[p + 2 * i + 1]) for i in range(nl)]; p += 2 * nl
     rover = st[p]; bitmap = st[p + 1] & ((1 << 64) - 1); p += 2
     lists = None
-    if algo == SEG_FIT:
+    if n_lists(algo):
         lists = []
-        for _ in range(64):
+        for _ in range(n_lists(algo)):
             n = st[p]; p += 1
             lists.append(st[p:p + n]); p += n
     assert p == len(st), "malformed state"

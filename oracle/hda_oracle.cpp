@@ -3,9 +3,11 @@
 // A plain, slow, sequential CPU model of the allocators in "Host-Based
 // Allocators for Device Memory" (Bell, Kumar, Gill): first fit, next fit and
 // best fit over an address-ordered free list (Sec. II-A, Sec. IV, Alg. 1-3),
-// and segregated fit over address-keyed block records threaded into per-class
+// segregated fit over address-keyed block records threaded into per-class
 // free lists with a class-availability bitmap (Sec. III-C, Sec. V-A,
-// Alg. 4-5).  No metadata lives in the managed memory: the arena is never
+// Alg. 4-5), and two-level segregated fit (TLSF, Sec. V-B), the same
+// machinery with each power-of-two class split linearly and a two-level
+// bitmap lookup.  No metadata lives in the managed memory: the arena is never
 // touched, only described.
 //
 // Only the test-suite, the smoke check and the CPU-baseline leg of the
@@ -39,21 +41,34 @@
 //    becomes empty.  On free, free neighbours are unlinked from their lists
 //    first and the merged block is always pushed at the head of the list of
 //    floor(log2 size).  The null link is -1 (offset 0 is a valid address).
+//  * TLSF (Sec. V-B; the paper gives no second-level count): every power of
+//    two is split into 32 linear sub-classes (second-level index 5, the
+//    default of the TLSF authors' implementation).  A block of b bytes is in
+//    class (fl, sl) with fl = floor(log2 b) and sl = (b >> (fl-5)) - 32
+//    (b << (5-fl) when fl < 5, so that each such class holds one size).  A
+//    request of s bytes is first rounded up to the next sub-class boundary,
+//    s + 2^(fl-5) - 1 for fl >= 5 (nothing below), and its class (fl, sl)
+//    taken from that; every block of that class or a higher one is then at
+//    least s.  The lookup consults the second-level bitmap of fl for a
+//    sub-class >= sl, and otherwise the first-level bitmap for the lowest
+//    fl' > fl and that level's lowest sub-class.  Lists, splitting, merging
+//    and pushing are those of segregated fit; a first-level bit is set
+//    exactly when one of its sub-class lists is non-empty.
 //  * No allocation ever fails with an error: a request nothing can satisfy
 //    returns -1 and leaves the state (and the rover) unchanged.
 //  * Partial deallocation (Sec. II-A, Alg. 2) is defined for the sequential
 //    fits only: freeing x inside the live block [b, b+s), b < x, shrinks it
 //    to [b, x) and releases [x, b+s) with the same merging as a whole block;
 //    the block keeps its place in live[].  x must be a multiple of g.
-//    Segregated fit frees exactly one keyed block (Alg. 5), so an interior
-//    address is a bad free there.
+//    Segregated fit and TLSF free exactly one keyed block (Alg. 5), so an
+//    interior address is a bad free there.
 //  * Replay driver (not part of the paper): a free request q < 0 carries
 //    u = ~q, a uniform 32-bit draw r = u mod 2^32 and a cut c = u >> 32
 //    (0 <= c < 2^31).  The victim is live[(r * L) >> 32] where live[] lists
 //    the live blocks (append on success, swap-with-last removal on a whole
 //    free) and L = |live|.  For the sequential fits the victim's first
 //    t = floor(c * (s / g) / 2^31) granules stay live and the rest is freed
-//    (t = 0: the whole block); segregated fit ignores c.  The result is the
+//    (t = 0: the whole block); segregated fit and TLSF ignore c.  The result is the
 //    byte address freed.  With no live block the request does nothing and
 //    yields -1.
 #include <algorithm>
@@ -65,7 +80,8 @@
 
 namespace {
 
-constexpr int FF = 0, NF = 1, BF = 2, SF = 3;
+constexpr int FF = 0, NF = 1, BF = 2, SF = 3, TLSF = 4;
+constexpr int SLI = 5, NSL = 1 << SLI;   // TLSF second level: 32 sub-classes
 constexpr int64_t NIL = -1;
 constexpr int E_INVAL = -2, E_BADFREE = -3;
 
@@ -98,18 +114,20 @@ struct Heap {
     // sequential fits: address-ordered free list, address -> size
     std::map<int64_t, int64_t> fl;
     int64_t rover = 0;
-    // segregated fit: address-keyed records, list heads, availability bitmap
+    // segregated fit / TLSF: address-keyed records, list heads, availability
+    // bitmap (TLSF: first level, plus one second-level bitmap per level)
     std::map<int64_t, SfRecord> ht;
-    int64_t head[64];
+    std::vector<int64_t> head;
     uint64_t bitmap = 0;
+    uint32_t sl_bitmap[64] = {};
     // instrumentation
     uint64_t examined = 0;    // free entries inspected by a fit search
     uint64_t touched = 0;     // segregated-fit records read or written
 
-    Heap(int a, int64_t arena, int64_t align) : algo(a), A(arena), g(align) {
+    Heap(int a, int64_t arena, int64_t align)
+        : algo(a), A(arena), g(align), head(a == TLSF ? 64 * NSL : 64, NIL) {
         // Alg. 6: the free list starts as the single block [0, A).
-        for (auto& h : head) h = NIL;
-        if (algo == SF) {
+        if (segregated()) {
             ht[0] = SfRecord{A, true, NIL, NIL, NIL};
             push(0);
         } else {
@@ -117,26 +135,78 @@ struct Heap {
         }
     }
 
+    bool segregated() const { return algo == SF || algo == TLSF; }
+
+    // ---- size classes ----
+    // TLSF class (fl, sl) of b >= 1 bytes, as the index fl * 32 + sl.
+    static int tlsf_class(uint64_t b) {
+        int fl = floor_log2(b);
+        uint64_t sl = fl >= SLI ? (b >> (fl - SLI)) - NSL : (b << (SLI - fl)) - NSL;
+        return fl * NSL + int(sl);
+    }
+    // The list a free block of `size` bytes belongs to.
+    int cls(int64_t size) const {
+        return algo == TLSF ? tlsf_class(uint64_t(size)) : floor_log2(uint64_t(size));
+    }
+    void mark(int c) {
+        if (algo == TLSF) {
+            sl_bitmap[c / NSL] |= uint32_t(1) << (c % NSL);
+            bitmap |= uint64_t(1) << (c / NSL);
+        } else {
+            bitmap |= uint64_t(1) << c;
+        }
+    }
+    void unmark(int c) {
+        if (algo == TLSF) {
+            sl_bitmap[c / NSL] &= ~(uint32_t(1) << (c % NSL));
+            if (sl_bitmap[c / NSL] == 0) bitmap &= ~(uint64_t(1) << (c / NSL));
+        } else {
+            bitmap &= ~(uint64_t(1) << c);
+        }
+    }
+
     // ---- segregated-fit list primitives (Alg. 4, Alg. 5) ----
     void push(int64_t a) {
         SfRecord& r = ht.at(a);
-        int c = floor_log2(uint64_t(r.size));
+        int c = cls(r.size);
         r.prev_free = NIL;
         r.next_free = head[c];
         if (head[c] != NIL) { ht.at(head[c]).prev_free = a; ++touched; }
         head[c] = a;
-        bitmap |= uint64_t(1) << c;
+        mark(c);
         ++touched;
     }
     void unlink(int64_t a) {
         SfRecord& r = ht.at(a);
-        int c = floor_log2(uint64_t(r.size));
+        int c = cls(r.size);
         if (r.prev_free != NIL) { ht.at(r.prev_free).next_free = r.next_free; ++touched; }
         else head[c] = r.next_free;
         if (r.next_free != NIL) { ht.at(r.next_free).prev_free = r.prev_free; ++touched; }
-        if (head[c] == NIL) bitmap &= ~(uint64_t(1) << c);
+        if (head[c] == NIL) unmark(c);
         r.next_free = r.prev_free = NIL;
         ++touched;
+    }
+
+    // The list an allocation of s bytes pops from, or -1 (Alg. 4's bitmap
+    // lookup; TLSF: the two-level lookup of Sec. V-B).
+    int find_list(int64_t s) const {
+        if (algo == SF) {
+            int k = ceil_log2(uint64_t(s));
+            uint64_t m = (k >= 64) ? 0 : (bitmap & (~uint64_t(0) << k));
+            return m == 0 ? -1 : __builtin_ctzll(m);
+        }
+        int f0 = floor_log2(uint64_t(s));
+        uint64_t r = uint64_t(s) + (f0 >= SLI ? (uint64_t(1) << (f0 - SLI)) - 1 : 0);
+        int c = tlsf_class(r), fl = c / NSL, sl = c % NSL;
+        if (fl >= 64) return -1;
+        uint32_t slm = sl_bitmap[fl] & (~uint32_t(0) << sl);
+        if (slm == 0) {
+            uint64_t flm = fl + 1 >= 64 ? 0 : (bitmap & (~uint64_t(0) << (fl + 1)));
+            if (flm == 0) return -1;
+            fl = __builtin_ctzll(flm);
+            slm = sl_bitmap[fl];
+        }
+        return fl * NSL + __builtin_ctz(slm);
     }
 
     // ---- allocation ----
@@ -145,7 +215,7 @@ struct Heap {
         int64_t s = (req + g - 1) / g * g;
         if (s == 0) s = g;
         if (s > A) return -1;
-        int64_t a = (algo == SF) ? alloc_sf(s) : alloc_seq(s);
+        int64_t a = segregated() ? alloc_sf(s) : alloc_seq(s);
         if (a >= 0) { used[a] = s; live.push_back(a); }
         return a;
     }
@@ -185,10 +255,8 @@ struct Heap {
     }
 
     int64_t alloc_sf(int64_t s) {
-        int k = ceil_log2(uint64_t(s));
-        uint64_t m = (k >= 64) ? 0 : (bitmap & (~uint64_t(0) << k));
-        if (m == 0) return -1;
-        int c = __builtin_ctzll(m);
+        int c = find_list(s);
+        if (c < 0) return -1;
         int64_t a = head[c];
         unlink(a);
         SfRecord& it = ht.at(a);
@@ -213,7 +281,7 @@ struct Heap {
         auto lv = std::find(live.begin(), live.end(), x);
         *lv = live.back();
         live.pop_back();
-        if (algo == SF) dealloc_sf(x); else dealloc_seq(x, s);
+        if (segregated()) dealloc_sf(x); else dealloc_seq(x, s);
         return 0;
     }
 
@@ -227,7 +295,7 @@ struct Heap {
         int64_t b = u->first, s = u->second;
         if (x >= b + s) return E_BADFREE;
         if (x == b) return dealloc(x);
-        if (algo == SF || x % g != 0) return E_BADFREE;
+        if (segregated() || x % g != 0) return E_BADFREE;
         u->second = x - b;           // it.size = addr - it.addr
         dealloc_seq(x, b + s - x);   // size -= it.size
         return 0;
@@ -283,12 +351,13 @@ struct Heap {
 
     // ---- canonical state ----
     // [n_free, (addr,size)*n_free by address, n_live, (addr,size)*n_live in
-    //  live order, rover (next fit) or -1, bitmap (segregated fit) or 0,
-    //  segregated fit only: for each class 0..63: len, addresses head->tail]
+    //  live order, rover (next fit) or -1, bitmap (segregated fit; TLSF: the
+    //  first level) or 0, segregated fit / TLSF only: for each list (64 or
+    //  64 * 32 of them, class index order): len, addresses head->tail]
     std::vector<int64_t> dump() const {
         std::vector<int64_t> o;
         std::vector<std::pair<int64_t, int64_t>> fb;
-        if (algo == SF) {
+        if (segregated()) {
             for (auto& kv : ht) if (kv.second.free) fb.push_back({kv.first, kv.second.size});
         } else {
             for (auto& kv : fl) fb.push_back(kv);
@@ -298,9 +367,9 @@ struct Heap {
         o.push_back(int64_t(live.size()));
         for (int64_t a : live) { o.push_back(a); o.push_back(used.at(a)); }
         o.push_back(algo == NF ? rover : -1);
-        o.push_back(algo == SF ? int64_t(bitmap) : 0);
-        if (algo == SF) {
-            for (int c = 0; c < 64; ++c) {
+        o.push_back(segregated() ? int64_t(bitmap) : 0);
+        if (segregated()) {
+            for (int c = 0; c < int(head.size()); ++c) {
                 std::vector<int64_t> lst;
                 for (int64_t a = head[c]; a != NIL; a = ht.at(a).next_free) lst.push_back(a);
                 o.push_back(int64_t(lst.size()));
@@ -312,7 +381,7 @@ struct Heap {
 };
 
 bool valid_params(int algo, int64_t arena, int64_t align) {
-    if (algo < 0 || algo > 3) return false;
+    if (algo < 0 || algo > 4) return false;
     if (align <= 0 || (align & (align - 1))) return false;
     if (arena <= 0 || arena % align) return false;
     if (arena / align >= (int64_t(1) << 32)) return false;
@@ -333,7 +402,7 @@ void replay_one(Heap& h, int64_t n, const int64_t* req, int64_t* res) {
             uint64_t idx = (r * uint64_t(h.live.size())) >> 32;
             int64_t x = h.live[idx];
             int64_t keep = 0;        // bytes of the victim that stay live
-            if (h.algo != SF) keep = int64_t((c * uint64_t(h.used.at(x) / h.g)) >> 31) * h.g;
+            if (!h.segregated()) keep = int64_t((c * uint64_t(h.used.at(x) / h.g)) >> 31) * h.g;
             if (keep == 0) {
                 h.dealloc(x);
             } else {

@@ -10,12 +10,23 @@ They share nothing with the oracle's code and use different representations:
 * Segregated fit keeps a Python list of all blocks (address, size, free) and
   64 plain Python lists as the class lists (head at index 0); neighbours are
   found by scanning the block list by address instead of following links.
+  TLSF is the same model over 64 x 32 classes given by an explicit sorted
+  table of class lower bounds (2^fl + sl * 2^fl / 32): a block belongs to the
+  last class whose bound it reaches, a request takes the first non-empty
+  class whose bound is at least its size -- bisection instead of the bit
+  arithmetic and two-level bitmaps of the oracle.
 
 Both are O(arena) per operation and meant for tiny heaps only.
 """
 from __future__ import annotations
 
-FIRST_FIT, NEXT_FIT, BEST_FIT, SEG_FIT = 0, 1, 2, 3
+import bisect
+
+FIRST_FIT, NEXT_FIT, BEST_FIT, SEG_FIT, TLSF = 0, 1, 2, 3, 4
+
+# class lower bounds, scaled by 32 so that the TLSF ones are integers
+SF_BOUNDS = [(1 << k) * 32 for k in range(64)]
+TLSF_BOUNDS = [(1 << fl) * (32 + sl) for fl in range(64) for sl in range(32)]
 
 
 def granules(req: int, g: int) -> int:
@@ -113,16 +124,15 @@ class BitmapHeap:
 class ListSegFit:
     """Segregated fit with a flat block list and 64 Python class lists."""
 
-    def __init__(self, arena: int, align: int):
-        self.A, self.g = arena, align
+    def __init__(self, arena: int, align: int, bounds=SF_BOUNDS):
+        self.A, self.g, self.bounds = arena, align, bounds
         self.blocks = [[0, arena, True]]          # [addr, size, free], by address
-        self.lists = [[] for _ in range(64)]      # addresses, head first
-        self.lists[arena.bit_length() - 1].insert(0, 0)
+        self.lists = [[] for _ in bounds]         # addresses, head first
+        self.lists[self.cls(arena)].insert(0, 0)
         self.live = []
 
-    @staticmethod
-    def cls(size: int) -> int:                    # size in [2^k, 2^(k+1))
-        return size.bit_length() - 1
+    def cls(self, size: int) -> int:              # last class whose bound size reaches
+        return bisect.bisect_right(self.bounds, size * 32) - 1
 
     def _find(self, addr):
         for i, b in enumerate(self.blocks):
@@ -134,8 +144,8 @@ class ListSegFit:
         if req > self.A:
             return -1
         s = granules(req, self.g) * self.g
-        k = (s - 1).bit_length()                  # smallest k with 2^k >= s
-        c = next((c for c in range(k, 64) if self.lists[c]), None)
+        k = bisect.bisect_left(self.bounds, s * 32)   # first class whose bound is >= s
+        c = next((c for c in range(k, len(self.lists)) if self.lists[c]), None)
         if c is None:
             return -1
         addr = self.lists[c].pop(0)
@@ -178,16 +188,21 @@ class ListSegFit:
     def state(self):
         sizes = {b[0]: b[1] for b in self.blocks}
         bitmap = 0
-        for c in range(64):
+        per_bit = len(self.lists) // 64           # TLSF: a bit per first level
+        for c in range(len(self.lists)):
             if self.lists[c]:
-                bitmap |= 1 << c
+                bitmap |= 1 << (c // per_bit)
         return dict(free=[(b[0], b[1]) for b in self.blocks if b[2]],
                     live=[(a, sizes[a]) for a in self.live],
                     rover=-1, bitmap=bitmap, lists=[list(l) for l in self.lists])
 
 
 def make(algo: int, arena: int, align: int):
-    return ListSegFit(arena, align) if algo == SEG_FIT else BitmapHeap(algo, arena, align)
+    if algo == SEG_FIT:
+        return ListSegFit(arena, align)
+    if algo == TLSF:
+        return ListSegFit(arena, align, TLSF_BOUNDS)
+    return BitmapHeap(algo, arena, align)
 
 
 def draw_index(q: int, n_live: int) -> int:

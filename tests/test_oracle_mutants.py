@@ -32,10 +32,10 @@ MUTANTS = [
     ("right_adjacency_index", "succ->first == x + s", "succ->first == x", 0),
     ("sf_request_class_floor", "int k = ceil_log2(uint64_t(s));",
      "int k = floor_log2(uint64_t(s));", 0),
-    ("sf_highest_class", "int c = __builtin_ctzll(m);", "int c = 63 - __builtin_clzll(m);", 0),
-    ("sf_bit_not_cleared", "if (head[c] == NIL) bitmap &= ~(uint64_t(1) << c);", "", 0),
-    ("sf_push_class_ceil", "int c = floor_log2(uint64_t(r.size));\n        r.prev_free = NIL;",
-     "int c = ceil_log2(uint64_t(r.size));\n        r.prev_free = NIL;", 0),
+    ("sf_highest_class", "return m == 0 ? -1 : __builtin_ctzll(m);",
+     "return m == 0 ? -1 : 63 - __builtin_clzll(m);", 0),
+    ("sf_bit_not_cleared", "            bitmap &= ~(uint64_t(1) << c);", "", 0),
+    ("sf_push_class_ceil", ": floor_log2(uint64_t(size));", ": ceil_log2(uint64_t(size));", 0),
     ("sf_unlink_drops_tail", "else head[c] = r.next_free;", "else head[c] = NIL;", 0),
     # (Writing l instead of l's own left link into the merged record is NOT a
     # mistake the state can show: that link is rewritten before it is ever read
@@ -53,14 +53,25 @@ MUTANTS = [
     ("partial_frees_whole_size", "dealloc_seq(x, b + s - x);", "dealloc_seq(x, s);", 0),
     ("partial_cut_scale", "h.g)) >> 31) * h.g;", "h.g)) >> 32) * h.g;", 0),
     ("partial_result_is_block_start", "res[i] = x + keep;", "res[i] = x;", 0),
-    ("partial_unaligned_accepted", "if (algo == SF || x % g != 0) return E_BADFREE;",
-     "if (algo == SF) return E_BADFREE;", 0),
-    ("partial_on_seg_fit", "if (algo == SF || x % g != 0) return E_BADFREE;",
+    ("partial_unaligned_accepted", "if (segregated() || x % g != 0) return E_BADFREE;",
+     "if (segregated()) return E_BADFREE;", 0),
+    ("partial_on_seg_fit", "if (segregated() || x % g != 0) return E_BADFREE;",
      "if (x % g != 0) return E_BADFREE;", 0),
-    ("partial_cut_on_wrong_algos", "if (h.algo != SF) keep", "if (h.algo == SF) keep", 0),
+    ("partial_cut_on_wrong_algos", "if (!h.segregated()) keep", "if (h.segregated()) keep", 0),
+    # TLSF (checked by its own pin file)
+    ("tlsf_no_round_up", "uint64_t r = uint64_t(s) + (f0 >= SLI ? (uint64_t(1) << (f0 - SLI)) - 1 : 0);",
+     "uint64_t r = uint64_t(s);", 0, "tlsf"),
+    ("tlsf_skips_a_level", "(bitmap & (~uint64_t(0) << (fl + 1)))", "(bitmap & (~uint64_t(0) << (fl + 2)))",
+     0, "tlsf"),
+    ("tlsf_sl_bit_not_cleared", "sl_bitmap[c / NSL] &= ~(uint32_t(1) << (c % NSL));", "", 0, "tlsf"),
+    ("tlsf_fl_bit_not_cleared",
+     "if (sl_bitmap[c / NSL] == 0) bitmap &= ~(uint64_t(1) << (c / NSL));", "", 0, "tlsf"),
+    ("tlsf_sub_class_from_low_bits", "(b >> (fl - SLI)) - NSL", "(b & (NSL - 1))", 0, "tlsf"),
 ]
 
-PINS = [os.path.join(ROOT, "tests", f) for f in ("test_oracle_pins.py", "test_oracle_partial.py")]
+PINS = {"seq": [os.path.join(ROOT, "tests", f)
+                for f in ("test_oracle_pins.py", "test_oracle_partial.py")],
+        "tlsf": [os.path.join(ROOT, "tests", "test_oracle_tlsf.py")]}
 
 
 def _replace_nth(text, old, new, n):
@@ -72,7 +83,8 @@ def _replace_nth(text, old, new, n):
 
 
 def _run(m, tmp):
-    name, old, new, n = m
+    name, old, new, n = m[:4]
+    pins = PINS[m[4] if len(m) > 4 else "seq"]
     src = open(SRC).read()
     mutated = _replace_nth(src, old, new, n)
     assert mutated != src
@@ -83,7 +95,7 @@ def _run(m, tmp):
     subprocess.check_call(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-pthread",
                            cpp, "-o", so])
     env = dict(os.environ, HDA_ORACLE_LIB=so)
-    p = subprocess.run([sys.executable, "-m", "pytest", *PINS, "-x", "-q",
+    p = subprocess.run([sys.executable, "-m", "pytest", *pins, "-x", "-q",
                         "-p", "no:cacheprovider", "--timeout", "120",
                         "-k", "not depth6"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
@@ -92,7 +104,7 @@ def _run(m, tmp):
 
 def test_every_anchor_is_unique_enough():
     src = open(SRC).read()
-    for name, old, _, n in MUTANTS:
+    for name, old, _, n, *_ in MUTANTS:
         assert src.count(old) > n, name
 
 
