@@ -37,7 +37,12 @@ enum {
   HDA_FIRST_FIT = 0, /* lowest-address free block with size >= s (Sec. II-A) */
   HDA_NEXT_FIT = 1,  /* first fit resumed at a rover (Sec. II-A, Sec. IV)    */
   HDA_BEST_FIT = 2,  /* smallest block >= s, lowest address on ties (Alg. 3) */
-  HDA_SEG_FIT = 3    /* power-of-two classes + bitmap, LIFO lists (Alg. 4-5) */
+  HDA_SEG_FIT = 3,   /* power-of-two classes + bitmap, LIFO lists (Alg. 4-5) */
+  HDA_TLSF = 4       /* two-level segregated fit (Sec. V-B): each power of two
+                        split into 32 linear sub-classes; a request is rounded
+                        up to the next sub-class bound and served from the
+                        first non-empty class at or above it (two-level
+                        bitmap lookup); lists as in segregated fit          */
 };
 
 /* Status codes. */
@@ -79,9 +84,15 @@ enum {
  *   n_free, (addr, size) x n_free in address order,
  *   n_live, (addr, size) x n_live in live[] order,
  *   rover (next fit: the byte address the next search resumes at) or -1,
- *   class bitmap (segregated fit; bit k <=> class k list non-empty) or 0,
- *   segregated fit only: for each class k = 0..63 (sizes in [2^k, 2^(k+1))):
- *     len_k, then the block addresses from list head to tail.
+ *   class bitmap (segregated fit: bit k <=> class k list non-empty; TLSF:
+ *     bit fl <=> one of the lists of level fl non-empty) or 0,
+ *   segregated fit: for each class k = 0..63 (sizes in [2^k, 2^(k+1))):
+ *     len_k, then the block addresses from list head to tail;
+ *   TLSF: the same for each class c = fl * 32 + sl = 0..2047, which holds
+ *     sizes b with floor(log2 b) = fl and (b >> (fl - 5)) - 32 = sl
+ *     ((b << (5 - fl)) - 32 below 32 bytes).
+ * A heap with n_req requests needs at most 4 + 4 * (n_req + 1) words, plus
+ * 64 + n_req + 1 for segregated fit and 2048 + n_req + 1 for TLSF.
  */
 /* Where each heap's tables live.  Default (lean) path: the first
  * 64*reg_free free-table entries are held in vector registers (reg_free = 1,
@@ -109,7 +120,7 @@ typedef struct hda_batch_desc {
   int64_t n_heaps;          /* H >= 0                                          */
   const int64_t *arena;     /* device [H]: arena bytes (> 0, multiple of align) */
   const int64_t *align;     /* device [H]: alignment bytes (power of two)       */
-  const int32_t *algo;      /* device [H]: HDA_FIRST_FIT .. HDA_SEG_FIT         */
+  const int32_t *algo;      /* device [H]: HDA_FIRST_FIT .. HDA_TLSF            */
   const int64_t *req_off;   /* device [H+1]: CSR offsets into req/res           */
   const int64_t *req;       /* device [req_off[H]]: encoded requests (non-null,
                                also when req_off[H] == 0)                       */

@@ -50,7 +50,7 @@ namespace hda {
 constexpr uint32_t kNone = 0xffffffffu;
 constexpr int64_t kFail = -1, kEInval = -2, kEBadFree = -3, kENoMeta = -4,
                   kERange = -7;
-enum : int { kFirstFit = 0, kNextFit = 1, kBestFit = 2, kSegFit = 3 };
+enum : int { kFirstFit = 0, kNextFit = 1, kBestFit = 2, kSegFit = 3, kTlsf = 4 };
 
 // Wave-wide minimum of a u32; every lane must be active.  Row-local
 // Hillis-Steele steps with DPP row shifts (identity shifted in) leave each
@@ -75,6 +75,29 @@ __device__ __forceinline__ uint32_t ceil_log2_u32(uint32_t x) {   // x >= 1
 }
 __device__ __forceinline__ uint32_t ctz64(uint64_t m) {           // m != 0
   return (uint32_t)__builtin_ctzll(m);
+}
+
+// Two-level segregated fit (Sec. V-B): each power of two of the byte size is
+// split into 2^kSli linear sub-classes.  A block of sg granules (sg >= 1, 2^shift
+// bytes each) belongs to class index fl * 2^kSli + sl, fl = floor(log2 bytes);
+// below 2^kSli bytes the sub-classes are finer than a byte and each holds
+// one size.  In granules sl does not depend on the shift.
+__host__ __device__ constexpr bool seg_like(int algo) { return algo == kSegFit || algo == kTlsf; }
+
+constexpr uint32_t kSli = 5, kNsl = 1u << kSli;
+constexpr uint32_t kTlsfClasses = 64u * kNsl;
+__device__ __forceinline__ uint32_t tlsf_class(uint64_t sg, uint32_t shift) {
+  const uint32_t lg = 63u - (uint32_t)__builtin_clzll(sg);
+  const uint64_t sl = lg >= kSli ? (sg >> (lg - kSli)) - kNsl : (sg << (kSli - lg)) - kNsl;
+  return (lg + shift) * kNsl + (uint32_t)sl;
+}
+// The class a request of sg granules is served from or above: its size
+// rounded up to the next sub-class bound, so that every block of that class
+// or a higher one fits (>= kTlsfClasses: nothing can).
+__device__ __forceinline__ uint32_t tlsf_request_class(uint32_t sg, uint32_t shift) {
+  const uint32_t lg = floor_log2_u32(sg);
+  const uint64_t r = (uint64_t)sg + (lg >= kSli ? (1ull << (lg - kSli)) - 1ull : 0ull);
+  return tlsf_class(r, shift);
 }
 
 // A table entry packs a block as (size << 32) | address, both in granules.
@@ -165,7 +188,10 @@ template <int ALGO, int RF, int RL>
 struct WaveHeap {
   static constexpr uint32_t HF = 64u * RF, HL = 64u * RL;
   static constexpr int NF = RF > 0 ? RF : 1, NL = RL > 0 ? RL : 1;
-  static constexpr bool kSeg = ALGO == kSegFit;
+  // segregated fit and TLSF: pushes are stamped; segregated fit alone keeps
+  // per-class counts (TLSF's 2,048 classes are found by a reduction instead)
+  static constexpr bool kSeg = ALGO == kSegFit || ALGO == kTlsf;
+  static constexpr bool kCounts = ALGO == kSegFit;
 
   Cold c;
   HeapRegs h;
@@ -281,8 +307,12 @@ struct WaveHeap {
   __device__ __forceinline__ uint32_t byte_class(uint32_t sg) const {
     return floor_log2_u32(sg) + h.shift;
   }
+  // the list a free block of sg granules belongs to
+  __device__ __forceinline__ uint32_t list_class(uint32_t sg) const {
+    return ALGO == kTlsf ? tlsf_class(sg, h.shift) : byte_class(sg);
+  }
   __device__ __forceinline__ void cnt_add(uint32_t cls, int d) {
-    h.cnt += (lane_id() == cls) ? (uint32_t)d : 0u;
+    if (kCounts) h.cnt += (lane_id() == cls) ? (uint32_t)d : 0u;
   }
   __device__ __forceinline__ uint64_t class_bitmap() const { return ballot(h.cnt != 0u); }
 
@@ -314,7 +344,7 @@ struct WaveHeap {
 
   // Selection (Sec. II, Sec. IV, Sec. V-A).  Returns the chosen entry's index
   // or kNone; (ja, js) receive its address and size.  seg_lo is the chosen
-  // class in granule terms (segregated fit only).
+  // class: in granule terms for segregated fit, the class index for TLSF.
   __device__ uint32_t select(uint32_t sg, uint32_t seg_lo, uint32_t& ja, uint32_t& js) {
     uint32_t k1 = kNone, k2 = kNone, bi = kNone, ba = 0, bs = 0;
     uint32_t w1 = kNone, wi = kNone, ws = 0;
@@ -339,8 +369,11 @@ struct WaveHeap {
         const bool wrap = fit && !past && a < w1;
         k1 = take ? a : k1; bi = take ? i : bi; bs = take ? s : bs;
         w1 = wrap ? a : w1; wi = wrap ? i : wi; ws = wrap ? s : ws;
-      } else {  // segregated fit: the class block pushed last
-        const bool take = v && (s >> seg_lo) == 1u && ~st < k1;
+      } else {  // segregated fit / TLSF: the class block pushed last
+        // (lanes past the table may hold size 0, which has no class)
+        const bool in = ALGO == kTlsf ? (v && s != 0u && list_class(s != 0u ? s : 1u) == seg_lo)
+                                      : (s >> seg_lo) == 1u;
+        const bool take = v && in && ~st < k1;
         k1 = take ? ~st : k1; bi = take ? i : bi; ba = take ? a : ba; bs = take ? s : bs;
       }
     });
@@ -365,21 +398,33 @@ struct WaveHeap {
       return rdlane(bi, wl);
     } else {
       const uint32_t wl = ctz64(m);
-      if constexpr (ALGO == kSegFit) ja = rdlane(ba, wl); else ja = K;
+      if constexpr (kSeg) ja = rdlane(ba, wl); else ja = K;
       js = rdlane(bs, wl);
       return rdlane(bi, wl);
     }
   }
 
   // Allocate sg granules (sg >= 1); k is the request's byte class for
-  // segregated fit.  Returns the byte offset, -1, or kENoMeta (no change).
+  // segregated fit, its request class for TLSF.  Returns the byte offset,
+  // -1, or kENoMeta (no change).
   __device__ int64_t alloc(uint32_t sg, uint32_t k) {
     uint32_t seg_lo = 0;
-    if constexpr (kSeg) {
+    if constexpr (ALGO == kSegFit) {
       if (k >= 64u) return kFail;
       const uint64_t m = class_bitmap() & (~0ull << k);
       if (m == 0ull) return kFail;
       seg_lo = ctz64(m) - h.shift;
+    } else if constexpr (ALGO == kTlsf) {
+      // the two-level bitmap lookup, as a reduction: the lowest class at or
+      // above k that holds a free block
+      if (k >= kTlsfClasses) return kFail;
+      uint32_t m = kNone;
+      scan_free([&](uint32_t, bool v, uint32_t, uint32_t s, uint32_t) {
+        const uint32_t c = (v && s != 0u) ? list_class(s != 0u ? s : 1u) : kNone;
+        m = (c >= k && c < m) ? c : m;
+      });
+      seg_lo = wave_min(m);
+      if (seg_lo == kNone) return kFail;
     }
     uint32_t a = 0, bs = 0;
     const uint32_t j = select(sg, seg_lo, a, bs);
@@ -545,7 +590,8 @@ struct WaveHeap {
     const uint64_t gm = (1ull << h.shift) - 1ull;
     uint32_t sg = (uint32_t)(((uint64_t)q + gm) >> h.shift);
     sg = sg == 0u ? 1u : sg;
-    return alloc(sg, ceil_log2_u32(sg) + h.shift);
+    return alloc(sg, ALGO == kTlsf ? tlsf_request_class(sg, h.shift)
+                                   : ceil_log2_u32(sg) + h.shift);
   }
 
   // Canonical state (format in hda.h), written by the whole wave.  The free
@@ -553,7 +599,8 @@ struct WaveHeap {
   // within each class.  Returns the number of words (written only if <= cap).
   __device__ int64_t dump(int64_t* out, int64_t cap) {
     const uint32_t lane = lane_id();
-    const int64_t need = 4 + 2 * (int64_t)h.F + 2 * (int64_t)h.L + (kSeg ? 64 + (int64_t)h.F : 0);
+    const int64_t lists = ALGO == kTlsf ? kTlsfClasses : 64;
+    const int64_t need = 4 + 2 * (int64_t)h.F + 2 * (int64_t)h.L + (kSeg ? lists + (int64_t)h.F : 0);
     if (out == nullptr || need > cap) return need;
     const uint32_t sh = h.shift;
     if (lane == 0) out[0] = h.F;
@@ -585,12 +632,51 @@ struct WaveHeap {
       }
     }
     int64_t* tail = lo + 1 + 2 * (int64_t)h.L;
-    const uint64_t bm = class_bitmap();
+    uint64_t bm = class_bitmap();
+    if constexpr (ALGO == kTlsf) {  // first level: the levels holding a free block
+      bm = 0ull;
+      for (uint32_t j = 0; j < h.F; ++j) {
+        uint32_t aj = 0, sj = 0;
+        fread(j, aj, sj);
+        bm |= 1ull << (list_class(sj) / kNsl);
+      }
+    }
     if (lane == 0) {
       tail[0] = ALGO == kNextFit ? (int64_t)((uint64_t)h.rover << sh) : -1;
       tail[1] = kSeg ? (int64_t)bm : 0;
     }
-    if constexpr (kSeg) {
+    if constexpr (ALGO == kTlsf) {
+      // list c starts at word c + (free blocks in lower classes); a block's
+      // place in its list is the number of same-class blocks pushed later
+      int64_t* ls = tail + 2;
+      for (uint32_t c0 = 0; c0 < kTlsfClasses; c0 += 64u) {
+        const uint32_t c = c0 + lane;
+        uint32_t below = 0, n = 0;
+        for (uint32_t j = 0; j < h.F; ++j) {
+          uint32_t aj = 0, sj = 0;
+          fread(j, aj, sj);
+          const uint32_t cj = list_class(sj);
+          below += cj < c ? 1u : 0u;
+          n += cj == c ? 1u : 0u;
+        }
+        ls[c + below] = n;
+      }
+      for (uint32_t base = 0; base < h.F; base += 64u) {
+        uint32_t a = 0, s = 0, st = 0;
+        fchunk_any(base, a, s, st);
+        const bool v = base + lane < h.F;
+        const uint32_t cls = (v && s != 0u) ? list_class(s != 0u ? s : 1u) : kNone;
+        uint32_t below = 0, rank = 0;
+        for (uint32_t j = 0; j < h.F; ++j) {
+          uint32_t aj = 0, sj = 0;
+          fread(j, aj, sj);
+          const uint32_t cj = list_class(sj), tj = stread(j);
+          below += cj < cls ? 1u : 0u;
+          rank += (cj == cls && tj > st) ? 1u : 0u;
+        }
+        if (v) ls[cls + below + 1u + rank] = (int64_t)((uint64_t)a << sh);
+      }
+    } else if constexpr (kSeg) {
       int64_t* ls = tail + 2;
       const uint32_t region = 64u + h.F;   // words of the class-list section
       // header position of class `lane`: sum over lower classes of (1 + count)

@@ -46,7 +46,8 @@ __global__ void heap_call(HeapHdr* hd, int op, int64_t arg, int64_t* out, int64_
     case kFirstFit: heap_call_t<kFirstFit>(hd, op, arg, out, cap); break;
     case kNextFit: heap_call_t<kNextFit>(hd, op, arg, out, cap); break;
     case kBestFit: heap_call_t<kBestFit>(hd, op, arg, out, cap); break;
-    default: heap_call_t<kSegFit>(hd, op, arg, out, cap); break;
+    case kSegFit: heap_call_t<kSegFit>(hd, op, arg, out, cap); break;
+    default: heap_call_t<kTlsf>(hd, op, arg, out, cap); break;
   }
 }
 
@@ -103,7 +104,7 @@ int hda_heap_create(uint64_t arena_bytes, uint64_t align, int algo, uint32_t met
                     hda_heap** out) {
   if (!out) return HDA_E_INVAL;
   *out = nullptr;
-  if (algo < HDA_FIRST_FIT || algo > HDA_SEG_FIT) return HDA_E_INVAL;
+  if (algo < HDA_FIRST_FIT || algo > HDA_TLSF) return HDA_E_INVAL;
   if (align == 0 || (align & (align - 1)) || arena_bytes == 0 || arena_bytes % align ||
       arena_bytes > (uint64_t)INT64_MAX || arena_bytes / align >= (uint64_t(1) << 32))
     return HDA_E_INVAL;

@@ -30,16 +30,22 @@
 namespace hda {
 
 constexpr int64_t kOverflow = -100;      // internal: the fast tiers are too small
-// Segregated-fit key of a free block: byte class in the top 6 bits and,
-// below, the push stamp taken from the all-ones value (kStampLimit - 1 -
-// stamp).  The smallest key at or above c << 26 is then the head (the block
-// pushed last) of the first non-empty class at or above c, so one wave-wide
-// minimum does Alg. 4's class search and list-head lookup together, and no
-// per-class counts are kept on the request path.  Stamps start at 1, so a
-// key never equals kNone, the key of an empty slot.
-constexpr uint32_t kKeyShift = 26;
-constexpr uint32_t kStampLimit = 1u << kKeyShift;
-constexpr uint32_t kStampMask = kStampLimit - 1u;
+// Segregated-fit key of a free block: the block's class in the top bits
+// (6 for the 64 byte classes of segregated fit, 11 for the 2,048 classes of
+// TLSF) and, below, the push stamp taken from the all-ones value (limit - 1 -
+// stamp).  The smallest key at or above c << shift is then the head (the
+// block pushed last) of the first non-empty class at or above c, so one
+// wave-wide minimum does Alg. 4's class search (TLSF: the two-level bitmap
+// lookup of Sec. V-B) and the list-head lookup together, and no per-class
+// counts are kept on the request path.  Stamps start at 1, so a key never
+// equals kNone, the key of an empty slot.
+template <int ALGO>
+struct SegKey {
+  static constexpr uint32_t kShift = ALGO == kTlsf ? 21u : 26u;
+  static constexpr uint32_t kLimit = 1u << kShift;   // stamps below this
+  static constexpr uint32_t kMask = kLimit - 1u;
+  static constexpr uint32_t kClasses = ALGO == kTlsf ? kTlsfClasses : 64u;
+};
 
 // Lane l of chunk r (both wave-uniform): every chunk's lane l is read and
 // the right one chosen on the scalar unit, which keeps the read free of
@@ -76,7 +82,11 @@ struct __attribute__((aligned(16))) SegRec {
 
 template <int ALGO, int RF>
 struct LeanHeap {
-  static constexpr bool kSeg = ALGO == kSegFit;
+  static constexpr bool kSeg = ALGO == kSegFit || ALGO == kTlsf;
+  static constexpr uint32_t kKeyShift = SegKey<ALGO>::kShift;
+  static constexpr uint32_t kStampLimit = SegKey<ALGO>::kLimit;
+  static constexpr uint32_t kStampMask = SegKey<ALGO>::kMask;
+  static constexpr uint32_t kClasses = SegKey<ALGO>::kClasses;
   static constexpr uint32_t HF = 64u * RF;
   static_assert(RF >= 1, "at least one register chunk");
 
@@ -131,14 +141,16 @@ struct LeanHeap {
     return (HDA_LDS Ent*)(m.base + m.bytes) - (i + 1u);
   }
 
-  __device__ __forceinline__ uint32_t byte_class(uint32_t sg) const {
-    return floor_log2_u32(sg) + shift;
+  // the list a free block of sg granules belongs to
+  __device__ __forceinline__ uint32_t list_class(uint32_t sg) const {
+    return ALGO == kTlsf ? tlsf_class(sg, shift) : floor_log2_u32(sg) + shift;
   }
   __device__ __forceinline__ uint32_t seg_key(uint32_t sg) {
-    return (byte_class(sg) << kKeyShift) | (clock++ ^ kStampMask);
+    return (list_class(sg) << kKeyShift) | (clock++ ^ kStampMask);
   }
-  // Lane k: the number of free blocks of byte class k (for the canonical
-  // state and the hand-over to the general core; not kept per request).
+  // Segregated fit, lane k: the number of free blocks of byte class k (for
+  // the canonical state and the hand-over to the general core; not kept per
+  // request).
   __device__ uint32_t class_counts() {
     uint32_t n = 0;
     for (uint32_t j = 0; j < F; ++j) {
@@ -318,7 +330,7 @@ struct LeanHeap {
       // segregated fit: the first non-empty class at or above the request's,
       // and in it the block pushed last (Alg. 4): the smallest key at or
       // above the request's class
-      if (kreq >= 64u) return false;
+      if (kreq >= kClasses) return false;
       const uint32_t lo = kreq << kKeyShift;
       uint32_t best = kNone, bc = 0;
       scan([&](uint32_t ch, uint32_t, uint32_t, uint32_t ek) {
@@ -447,7 +459,7 @@ struct LeanHeap {
   // beside it, every live entry i to device slot i.
   __device__ void migrate(const Cold& c, HeapRegs& h) {
     const uint32_t lane = lane_id();
-    const uint32_t counts = kSeg ? class_counts() : 0u;
+    const uint32_t counts = ALGO == kSegFit ? class_counts() : 0u;
     for (uint32_t ch = RF; 64u * ch < F; ++ch) {
       const uint32_t gi = 64u * ch + lane;
       wave_sync();
@@ -483,7 +495,7 @@ struct LeanHeap {
   // Canonical state, same format as the general core (hda.h).
   __device__ int64_t dump(int64_t* out, int64_t cap) {
     const uint32_t lane = lane_id();
-    const int64_t need = 4 + 2 * (int64_t)F + 2 * (int64_t)L + (kSeg ? 64 + (int64_t)F : 0);
+    const int64_t need = 4 + 2 * (int64_t)F + 2 * (int64_t)L + (kSeg ? kClasses + (int64_t)F : 0);
     if (out == nullptr || need > cap) return need;
     const uint32_t sh = shift;
     if (lane == 0) out[0] = F;
@@ -514,13 +526,49 @@ struct LeanHeap {
       }
     }
     int64_t* tail = lo + 1 + 2 * (int64_t)L;
-    const uint32_t cnt = kSeg ? class_counts() : 0u;
-    const uint64_t bm = ballot(cnt != 0u);
+    const uint32_t cnt = ALGO == kSegFit ? class_counts() : 0u;
+    uint64_t bm = ballot(cnt != 0u);
+    if constexpr (ALGO == kTlsf) {  // first level: the levels holding a free block
+      bm = 0ull;
+      for (uint32_t j = 0; j < F; ++j) {
+        uint32_t aj, sj, kj;
+        read(j, aj, sj, kj);
+        bm |= 1ull << ((kj >> kKeyShift) / kNsl);
+      }
+    }
     if (lane == 0) {
       tail[0] = ALGO == kNextFit ? (int64_t)((uint64_t)rover << sh) : -1;
       tail[1] = kSeg ? (int64_t)bm : 0;
     }
-    if constexpr (kSeg) {
+    if constexpr (ALGO == kTlsf) {
+      // list c starts at word c + (free blocks in lower classes); a block's
+      // place in its list is the number of same-class blocks pushed later
+      // (smaller keys)
+      int64_t* ls = tail + 2;
+      for (uint32_t c0 = 0; c0 < kClasses; c0 += 64u) {
+        const uint32_t cl = c0 + lane;
+        uint32_t below = 0, n = 0;
+        for (uint32_t j = 0; j < F; ++j) {
+          uint32_t aj, sj, kj;
+          read(j, aj, sj, kj);
+          below += (kj >> kKeyShift) < cl ? 1u : 0u;
+          n += (kj >> kKeyShift) == cl ? 1u : 0u;
+        }
+        ls[cl + below] = n;
+      }
+      scan([&](uint32_t c, uint32_t a, uint32_t, uint32_t key) {
+        const bool v = 64u * c + lane < F;
+        const uint32_t cls = key >> kKeyShift;
+        uint32_t below = 0, rank = 0;
+        for (uint32_t j = 0; j < F; ++j) {
+          uint32_t aj, sj, kj;
+          read(j, aj, sj, kj);
+          below += (kj >> kKeyShift) < cls ? 1u : 0u;
+          rank += ((kj >> kKeyShift) == cls && kj < key) ? 1u : 0u;
+        }
+        if (v) ls[cls + below + 1u + rank] = (int64_t)((uint64_t)a << sh);
+      });
+    } else if constexpr (kSeg) {
       int64_t* ls = tail + 2;
       const uint32_t region = 64u + F;  // words of the class-list section
       // header position of class `lane`: sum over lower classes of (1 + count)

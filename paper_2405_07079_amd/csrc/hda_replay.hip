@@ -49,7 +49,7 @@ struct ClassifyParams {
 __device__ __forceinline__ bool params_valid(const ClassifyParams& q, int64_t heap) {
   const int64_t A = q.arena[heap], g = q.align[heap];
   const int algo = q.algo[heap];
-  return !(algo < 0 || algo > 3 || g <= 0 || (g & (g - 1)) || A <= 0 || (A % g) ||
+  return !(algo < 0 || algo > kTlsf || g <= 0 || (g & (g - 1)) || A <= 0 || (A % g) ||
            (A / g) >= (int64_t(1) << 32));
 }
 
@@ -168,7 +168,8 @@ __global__ void __launch_bounds__(1024) lean_kernel(ReplayParams p) {
       case kFirstFit: lean_one_heap<kFirstFit, RF>(p, lds, c, heap); break;
       case kNextFit: lean_one_heap<kNextFit, RF>(p, lds, c, heap); break;
       case kBestFit: lean_one_heap<kBestFit, RF>(p, lds, c, heap); break;
-      default: lean_one_heap<kSegFit, RF>(p, lds, c, heap); break;
+      case kSegFit: lean_one_heap<kSegFit, RF>(p, lds, c, heap); break;
+      default: lean_one_heap<kTlsf, RF>(p, lds, c, heap); break;
     }
   });
 }

@@ -42,7 +42,7 @@ struct ReplayParams {
 __device__ __forceinline__ bool heap_params(const ReplayParams& p, int64_t heap, HeapRegs& h) {
   const int64_t A = p.arena[heap], g = p.align[heap];
   const int algo = p.algo[heap];
-  if (algo < 0 || algo > 3 || g <= 0 || (g & (g - 1)) || A <= 0 || (A % g) ||
+  if (algo < 0 || algo > kTlsf || g <= 0 || (g & (g - 1)) || A <= 0 || (A % g) ||
       (A / g) >= (int64_t(1) << 32))
     return false;
   h.algo = algo;
@@ -73,7 +73,7 @@ __device__ __forceinline__ uint32_t run_block(Core& w, uint32_t n, uint32_t w0, 
     } else if (v0 == 0u) {
       r = kFail;
     } else {
-      r = w.alloc(v0, ALGO == kSegFit ? rdlane(w1, j) : 0u);
+      r = w.alloc(v0, seg_like(ALGO) ? rdlane(w1, j) : 0u);
     }
     if (r == kOverflow) { done = j; break; }
     if (r == kENoMeta && st == 0) st = (int32_t)kENoMeta;
@@ -108,8 +108,10 @@ __device__ int64_t run_requests(const ReplayParams& p, Core& w, int64_t from, in
     uint32_t sg = (uint32_t)(((uint64_t)q + gm) >> shift);
     sg = sg == 0u ? 1u : sg;
     const uint32_t w0 = is_free ? (uint32_t)~(uint64_t)q : (big ? 0u : sg);
-    // segregated fit: the byte class; the other fits: a free's cut
+    // segregated fit: the byte class; TLSF: the request class; the other
+    // fits: a free's cut
     const uint32_t w1 = ALGO == kSegFit ? ceil_log2_u32(sg) + shift
+                      : ALGO == kTlsf   ? tlsf_request_class(sg, shift)
                                         : (is_free ? (uint32_t)(~(uint64_t)q >> 32) : 0u);
     const uint64_t mfree = ballot(is_free);
     const uint32_t n = (uint32_t)min<int64_t>(64, to - base);
@@ -117,8 +119,8 @@ __device__ int64_t run_requests(const ReplayParams& p, Core& w, int64_t from, in
     // a block whose frees carry no cut runs a copy with the partial-free
     // logic folded away
     const uint32_t done =
-        (ALGO != kSegFit && ballot(is_free && w1 != 0u) != 0ull)
-            ? run_block<ALGO, ALGO != kSegFit>(w, n, w0, w1, mfree, olo, ohi, st)
+        (!seg_like(ALGO) && ballot(is_free && w1 != 0u) != 0ull)
+            ? run_block<ALGO, !seg_like(ALGO)>(w, n, w0, w1, mfree, olo, ohi, st)
             : run_block<ALGO, false>(w, n, w0, w1, mfree, olo, ohi, st);
     if (lane < done) p.res[base + lane] = (int64_t)(((uint64_t)ohi << 32) | olo);
     if (done < n) return base + done;
@@ -220,7 +222,8 @@ __device__ void replay_any_heap(const ReplayParams& p, const Cold& c, int64_t he
     case kFirstFit: replay_heap<kFirstFit, RF, RL>(p, c, h, heap); break;
     case kNextFit: replay_heap<kNextFit, RF, RL>(p, c, h, heap); break;
     case kBestFit: replay_heap<kBestFit, RF, RL>(p, c, h, heap); break;
-    default: replay_heap<kSegFit, RF, RL>(p, c, h, heap); break;
+    case kSegFit: replay_heap<kSegFit, RF, RL>(p, c, h, heap); break;
+    default: replay_heap<kTlsf, RF, RL>(p, c, h, heap); break;
   }
 }
 

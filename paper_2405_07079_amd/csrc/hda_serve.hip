@@ -126,7 +126,8 @@ __device__ int64_t serve_one(const ServeParams& p, int32_t slot_id, int op, int6
     case kFirstFit: return run_op<kFirstFit>(slot, p, h, op, arg);
     case kNextFit: return run_op<kNextFit>(slot, p, h, op, arg);
     case kBestFit: return run_op<kBestFit>(slot, p, h, op, arg);
-    default: return run_op<kSegFit>(slot, p, h, op, arg);
+    case kSegFit: return run_op<kSegFit>(slot, p, h, op, arg);
+    default: return run_op<kTlsf>(slot, p, h, op, arg);
   }
 }
 
@@ -280,7 +281,7 @@ int wait_ticket(hda_server* s, uint64_t t, int64_t* result) {
 }
 
 bool arena_ok(uint64_t arena, uint64_t align, int algo) {
-  return algo >= HDA_FIRST_FIT && algo <= HDA_SEG_FIT && align != 0 && !(align & (align - 1)) &&
+  return algo >= HDA_FIRST_FIT && algo <= HDA_TLSF && align != 0 && !(align & (align - 1)) &&
          arena != 0 && arena % align == 0 && arena <= (uint64_t)INT64_MAX &&
          arena / align < (uint64_t(1) << 32);
 }

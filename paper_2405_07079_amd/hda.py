@@ -16,7 +16,7 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libhda.so")
 
-FIRST_FIT, NEXT_FIT, BEST_FIT, SEG_FIT = 0, 1, 2, 3
+FIRST_FIT, NEXT_FIT, BEST_FIT, SEG_FIT, TLSF = 0, 1, 2, 3, 4
 HDA_OK, HDA_FAIL, HDA_E_INVAL, HDA_E_BADFREE = 0, -1, -2, -3
 HDA_E_NOMETA, HDA_E_DEVICE, HDA_E_BUSY, HDA_E_RANGE = -4, -5, -6, -7
 
@@ -227,7 +227,8 @@ def state_words(algo, blocks):
     """Words of a canonical state dump with at most `blocks` free + live blocks."""
     algo = np.asarray(algo)
     blocks = np.asarray(blocks, dtype=np.int64)
-    return 4 + 2 * blocks + np.where(algo == SEG_FIT, 64 + blocks, 0)
+    return 4 + 2 * blocks + np.where(algo == SEG_FIT, 64 + blocks,
+                                     np.where(algo == TLSF, 2048 + blocks, 0))
 
 
 def upload(batch, device="cuda", order="lpt", with_state=True, meta_free=4096,

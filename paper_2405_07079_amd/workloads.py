@@ -29,9 +29,9 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-FIRST_FIT, NEXT_FIT, BEST_FIT, SEG_FIT = 0, 1, 2, 3
+FIRST_FIT, NEXT_FIT, BEST_FIT, SEG_FIT, TLSF = 0, 1, 2, 3, 4
 ALGO_NAMES = {FIRST_FIT: "first_fit", NEXT_FIT: "next_fit",
-              BEST_FIT: "best_fit", SEG_FIT: "seg_fit"}
+              BEST_FIT: "best_fit", SEG_FIT: "seg_fit", TLSF: "tlsf"}
 
 KiB, MiB, GiB = 1 << 10, 1 << 20, 1 << 30
 

@@ -50,7 +50,8 @@ def replay(batch, kf=64, kl=64, cf=4096, cl=4096, shape=2, overflowed=None):
     req = np.ascontiguousarray(batch.req, np.int64)
     res = np.full(req.shape, 0x7777, np.int64)
     lens = np.diff(off)
-    caps = 4 + 2 * (lens + 1) + np.where(algo == 3, 64 + lens + 1, 0)
+    caps = 4 + 2 * (lens + 1) + np.where(algo == 3, 64 + lens + 1,
+                                         np.where(algo == 4, 2048 + lens + 1, 0))
     so = np.zeros(H + 1, np.int64)
     np.cumsum(caps, out=so[1:])
     state = np.zeros(int(so[-1]), np.int64)

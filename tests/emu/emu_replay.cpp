@@ -36,7 +36,8 @@ void lean_any(const ReplayParams& p, const LeanLds& lds, const Cold& c, int64_t 
     case kFirstFit: lean_one_heap<kFirstFit, RF>(p, lds, c, heap); break;
     case kNextFit: lean_one_heap<kNextFit, RF>(p, lds, c, heap); break;
     case kBestFit: lean_one_heap<kBestFit, RF>(p, lds, c, heap); break;
-    default: lean_one_heap<kSegFit, RF>(p, lds, c, heap); break;
+    case kSegFit: lean_one_heap<kSegFit, RF>(p, lds, c, heap); break;
+    default: lean_one_heap<kTlsf, RF>(p, lds, c, heap); break;
   }
 }
 

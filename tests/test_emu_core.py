@@ -9,7 +9,7 @@ import emu
 import oracle
 from paper_2405_07079_amd import workloads as W
 
-ALGOS = (0, 1, 2, 3)
+ALGOS = (0, 1, 2, 3, 4)
 
 
 def check(batch, res, states, status, heaps=None):
@@ -51,7 +51,7 @@ def test_random_small_heaps():
         gran = int(rng.integers(1, 120))
         parts.append(W.random_tiny(int(rng.integers(1 << 30)), int(rng.integers(0, 300)),
                                    gran, align=int(1 << rng.integers(0, 12)),
-                                   algo=int(rng.integers(0, 4)),
+                                   algo=int(rng.integers(0, 5)),
                                    max_granules=max(1, gran // int(rng.integers(1, 6)))))
     b = W.concat(parts)
     res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=512, cl=512, shape=1)
@@ -152,7 +152,7 @@ def test_lean_random_small_heaps():
         gran = int(rng.integers(1, 400))
         parts.append(W.random_tiny(int(rng.integers(1 << 30)), int(rng.integers(0, 400)),
                                    gran, align=int(1 << rng.integers(0, 12)),
-                                   algo=int(rng.integers(0, 4)),
+                                   algo=int(rng.integers(0, 5)),
                                    max_granules=max(1, gran // int(rng.integers(1, 8)))))
     b = W.concat(parts)
     ovf = np.zeros(b.heaps, np.uint8)
@@ -215,7 +215,7 @@ def test_partial_frees_random_small_heaps():
         gran = int(rng.integers(1, 400))
         parts.append(W.random_tiny(int(rng.integers(1 << 30)), int(rng.integers(0, 400)),
                                    gran, align=int(1 << rng.integers(0, 12)),
-                                   algo=int(rng.integers(0, 4)),
+                                   algo=int(rng.integers(0, 5)),
                                    max_granules=max(1, gran // int(rng.integers(1, 8))),
                                    p_partial=float(rng.uniform(0.1, 1.0))))
     b = W.concat(parts)

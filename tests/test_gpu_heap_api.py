@@ -10,7 +10,7 @@ pytestmark = pytest.mark.gpu
 pytest.importorskip("torch")
 
 
-@pytest.mark.parametrize("algo", (0, 1, 2, 3))
+@pytest.mark.parametrize("algo", (0, 1, 2, 3, 4))
 def test_calls_match_oracle(algo):
     print(f"case: call-by-call heap algo {algo}", flush=True)
     A, g = 1 << 16, 32
@@ -34,7 +34,7 @@ def test_calls_match_oracle(algo):
     gh.close()
 
 
-@pytest.mark.parametrize("algo", (0, 1, 2, 3))
+@pytest.mark.parametrize("algo", (0, 1, 2, 3, 4))
 def test_arena_of_2_32_minus_1_granules(algo):
     """The largest arena a heap may have: the whole free arena's size and the
     end of its last block are both 2^32 - 1 granules."""
@@ -60,7 +60,7 @@ def test_arena_of_2_32_minus_1_granules(algo):
     gh.close()
 
 
-@pytest.mark.parametrize("algo", (0, 1, 2, 3))
+@pytest.mark.parametrize("algo", (0, 1, 2, 3, 4))
 def test_partial_free_calls_match_oracle(algo):
     """hda_free_partial at random offsets (block starts, interior granule
     boundaries, unaligned, free space) against the oracle's partial free."""

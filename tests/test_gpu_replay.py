@@ -11,7 +11,7 @@ from paper_2405_07079_amd import workloads as W
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-ALGOS = (0, 1, 2, 3)
+ALGOS = (0, 1, 2, 3, 4)
 
 
 def say(*a):
@@ -60,7 +60,7 @@ def random_small_batch(seed, heaps, max_len=1500):
         gran = int(rng.integers(1, 300))
         align = int(1 << rng.integers(0, 13))
         n = int(rng.integers(0, max_len)) if h % 17 else 0
-        algo = int(rng.integers(0, 4))
+        algo = int(rng.integers(0, 5))
         parts.append(W.random_tiny(int(rng.integers(1 << 30)), n, gran, align=align,
                                    p_alloc=float(rng.uniform(0.4, 0.75)), algo=algo,
                                    max_granules=max(1, gran // int(rng.integers(1, 8)))))
