@@ -117,6 +117,8 @@ def main():
     ap.add_argument("--tuning", type=str, default="0,0,0,0,0,0",
                     help="heaps_per_group,reg_free,reg_live,lds_free,lds_live,groups "
                          "(0 = default, -1 = none)")
+    ap.add_argument("--no-tlsf", action="store_true",
+                    help="skip the leg that replays the batch with two-level segregated fit")
     ap.add_argument("--partial-frees", type=float, default=0.02,
                     help="fraction of frees that are partial (Alg. 2) in the partial-"
                          "deallocation leg, a best-fit batch of the same shape (0: skip)")
@@ -217,6 +219,31 @@ def main():
     per_heap_value = ph_ops / ph_time
     log(f"[bench] per-heap launches: {per_heap_value / 1e6:.2f} M ops/s on {S} heaps/algo")
 
+    tlsf = None
+    if not args.no_tlsf:
+        # the same batch replayed with two-level segregated fit (Sec. V-B)
+        tdb = hda.upload(batch.with_algo(W.TLSF), tuning=tuning, share=dbs[algos[0]])
+        hda.hda_replay(tdb, stream)
+        torch.cuda.synchronize()
+        if int((tdb.status != 0).sum().item()):
+            raise RuntimeError("TLSF leg: heaps reported errors")
+        tms = []
+        for _ in range(max(1, args.steps)):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            hda.hda_replay(tdb, stream)
+            e1.record(stream)
+            tms.append((e0, e1))
+        torch.cuda.synchronize()
+        tms = [a.elapsed_time(b) for a, b in tms]
+        tlsf = {"workload": f"the batch above replayed with two-level segregated fit "
+                            f"(32 sub-classes per power of two)",
+                "value": batch.requests / (float(np.median(tms)) / 1e3), "unit": "ops/s",
+                "launch_ms": float(np.median(tms))}
+        del tdb
+        log(f"[bench] tlsf: {tlsf['value'] / 1e9:.3f} G ops/s")
+
     partial = None
     if args.partial_frees > 0:
         # the same batch shape on best fit, with that fraction of the frees
@@ -293,6 +320,15 @@ def main():
                          f"{csub.requests * len(algos)} requests, {ct:.1f} s wall "
                          f"on {cores} threads"}
         log(f"[bench] cpu oracle: {cpu['value'] / 1e6:.2f} M ops/s on {cores} threads")
+        if tlsf is not None:
+            tsub = csub.with_algo(W.TLSF)
+            t1 = time.perf_counter()
+            oracle.replay_batch(tsub, threads=cores, want_state=True)
+            tt = time.perf_counter() - t1
+            tlsf["cpu_baseline"] = {"value": tsub.requests / tt, "unit": "ops/s",
+                                    "cores": cores, "kind": "oracle",
+                                    "sample": f"first {tsub.heaps} heaps, {tsub.requests} "
+                                              f"requests, {tt:.1f} s wall"}
         if partial is not None:
             psub = pb.subset(np.arange(min(256, pb.heaps)))
             t1 = time.perf_counter()
@@ -344,6 +380,7 @@ def main():
                      "avg_launch_ms": avg_launch_s * 1e3,
                      "bytes_per_request": BYTES_PER_REQUEST,
                      "requests_per_launch": batch.requests},
+        "tlsf": tlsf,
         "partial_free": partial,
         "serving": serving,
         "cpu_baseline": cpu,

@@ -2,8 +2,8 @@
 uses, checked on heaps the oracle replays one by one (and, for the service,
 on properties that hold at any size).
 
-* 4,096 heaps x 100,000 requests (16 MiB arenas), best fit and segregated
-  fit, default tuning, states dumped: 24 sampled heaps per algorithm
+* 4,096 heaps x 100,000 requests (16 MiB arenas), best fit, segregated
+  fit and TLSF, default tuning, states dumped: 24 sampled heaps per algorithm
   (including the first and the last) compared element by element.
 * The same batch on best fit with 2 % of the frees partial: 24 sampled heaps.
 * The uneven batch (16,384 heaps, 46.9 M requests), autotuned and launched
@@ -47,7 +47,7 @@ def c2():
     return W.uniform_batch()
 
 
-@pytest.mark.parametrize("algo", (W.BEST_FIT, W.SEG_FIT))
+@pytest.mark.parametrize("algo", (W.BEST_FIT, W.SEG_FIT, W.TLSF))
 def test_4096_heaps_full_size_sampled(c2, algo):
     b = c2.with_algo(algo)
     say(f"case: 4096 x 16 MiB heaps, 100k requests each, algo {algo}")
