@@ -97,6 +97,99 @@ def host_cores():
         return os.cpu_count() or 1
 
 
+def paper_analog(W, torch):
+    """The paper's comparison with the vendor's allocation calls, on this
+    device: one stand-in trace (random allocations of 1 kB-16 MB and frees,
+    5,000 steps) replayed call by call through hipMalloc / hipFree and
+    through one of this library's segregated-fit heaps (4 GiB, 4 KiB
+    granules; one kernel launch per call), each timed per call by a C++
+    harness.  Fragmentation is 1 - in use / provisioned, where in use is the
+    bytes the live requests asked for and provisioned is the device memory
+    the process holds beyond its start (vendor; hipMemGetInfo) or the
+    highest offset the heap has handed out (ours), averaged over the second
+    half of the run."""
+    import ctypes
+    from paper_2405_07079_amd import build as hip_build
+    A = ctypes.CDLL(hip_build.ANALOG)
+    vp, i64, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64
+    A.hda_analog_vendor.restype = ctypes.c_int
+    A.hda_analog_vendor.argtypes = [vp, i64, vp, vp, vp]
+    A.hda_analog_heap.restype = ctypes.c_int
+    A.hda_analog_heap.argtypes = [vp, i64, u64, u64, ctypes.c_int, ctypes.c_uint32, vp, vp]
+    tb = W.paper_analog()
+    req = np.ascontiguousarray(tb.req, np.int64)
+    n = len(req)
+    arena, align, algo = int(tb.arena[0]), int(tb.align[0]), int(tb.algo[0])
+
+    def vendor(used=None):
+        lat, res = np.zeros(n, np.int64), np.zeros(n, np.int64)
+        rc = A.hda_analog_vendor(req.ctypes.data, n, lat.ctypes.data, res.ctypes.data,
+                                 None if used is None else used.ctypes.data)
+        if rc:
+            raise RuntimeError(f"vendor replay failed: {rc}")
+        return lat, res
+
+    def ours():
+        lat, res = np.zeros(n, np.int64), np.zeros(n, np.int64)
+        rc = A.hda_analog_heap(req.ctypes.data, n, arena, align, algo, 8192,
+                               lat.ctypes.data, res.ctypes.data)
+        if rc:
+            raise RuntimeError(f"heap replay failed: {rc}")
+        return lat, res
+
+    torch.cuda.synchronize()
+    vendor()                                   # the first calls set up the runtime's pools
+    vlat, vres = vendor()
+    free0, total = torch.cuda.mem_get_info()
+    used = np.zeros(n, np.int64)
+    vendor(used)
+    ours()
+    olat, ores = ours()
+
+    def in_use(res):
+        live, cur, out = [], 0, np.zeros(n, np.int64)
+        for i, q in enumerate(req.tolist()):
+            if q >= 0 and res[i] >= 0:
+                live.append(q)
+                cur += q
+            elif q < 0 and live:
+                k = (((~q) & 0xFFFFFFFF) * len(live)) >> 32
+                cur -= live[k]
+                live[k] = live[-1]
+                live.pop()
+            out[i] = cur
+        return out
+
+    def lat_stats(lat, mask):
+        x = lat[mask] / 1e3
+        return float(np.percentile(x, 50)), float(np.percentile(x, 99)), float(x.max())
+
+    def frag(use, prov):
+        h = np.arange(n) >= n // 2
+        ok = h & (prov > 0)
+        return float(np.mean(1.0 - use[ok] / prov[ok]))
+
+    allocs, frees = req >= 0, (req < 0) & (vlat > 0)
+    v_use, o_use = in_use(vres), in_use(ores)
+    v_prov = used - (total - free0)
+    ends = np.where(allocs & (ores >= 0), ores + -(-req // align) * align, 0)
+    o_prov = np.maximum.accumulate(ends)
+    out = {"workload": f"{n} steps, alloc p={tb.meta['p_alloc']}, sizes log-uniform "
+                       "1 KiB-16 MiB, frees of uniformly drawn live blocks; ours: one "
+                       "segregated-fit heap of 4 GiB with 4 KiB granules, call by call"}
+    for name, lat, use, prov, res in (("ours", olat, o_use, o_prov, ores),
+                                      ("vendor", vlat, v_use, v_prov, vres)):
+        a50, a99, amax = lat_stats(lat, allocs)
+        f50, f99, fmax = lat_stats(lat, frees)
+        out[name] = {"alloc_p50_us": a50, "alloc_p99_us": a99, "alloc_max_us": amax,
+                     "free_p50_us": f50, "free_p99_us": f99, "free_max_us": fmax,
+                     "allocs_failed": int((allocs & (res < 0)).sum()),
+                     "peak_in_use_mib": float(use.max()) / 2**20,
+                     "peak_provisioned_mib": float(prov.max()) / 2**20,
+                     "fragmentation": frag(use, prov)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +210,8 @@ def main():
     ap.add_argument("--tuning", type=str, default="0,0,0,0,0,0",
                     help="heaps_per_group,reg_free,reg_live,lds_free,lds_live,groups "
                          "(0 = default, -1 = none)")
+    ap.add_argument("--no-paper-analog", action="store_true",
+                    help="skip the per-call comparison with hipMalloc / hipFree")
     ap.add_argument("--no-tlsf", action="store_true",
                     help="skip the leg that replays the batch with two-level segregated fit")
     ap.add_argument("--partial-frees", type=float, default=0.02,
@@ -298,6 +393,12 @@ def main():
         log(f"[bench] serving at {args.serve_rate:.3g}/s: {rep['throughput']:.3g}/s, "
             f"p50 {rep['p50_us']:.1f} us, p99 {rep['p99_us']:.1f} us")
 
+    analog = None
+    if not args.no_paper_analog:
+        analog = paper_analog(W, torch)
+        log(f"[bench] paper analog: ours alloc p50 {analog['ours']['alloc_p50_us']:.1f} us, "
+            f"hipMalloc p50 {analog['vendor']['alloc_p50_us']:.1f} us")
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -382,6 +483,7 @@ def main():
                      "requests_per_launch": batch.requests},
         "tlsf": tlsf,
         "partial_free": partial,
+        "paper_analog": analog,
         "serving": serving,
         "cpu_baseline": cpu,
     }

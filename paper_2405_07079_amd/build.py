@@ -16,6 +16,11 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
          "-Wall", "-Wno-unused-function"]
 
 
+# the per-call latency harness of the benchmark's vendor comparison: host
+# code only, linked against libhda.so
+ANALOG = os.path.join(PKG, "libhda_analog.so")
+
+
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + f".tmp{os.getpid()}"
@@ -25,6 +30,14 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd))
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    tmp = ANALOG + f".tmp{os.getpid()}"
+    cmd = [HIPCC, "-O2", "-std=c++17", "-fPIC", "-shared", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(ROOT, "include"), os.path.join(CSRC, "hda_analog.cpp"),
+           "-L", PKG, "-lhda", "-Wl,-rpath,$ORIGIN", "-o", tmp]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(tmp, ANALOG)
     return LIB
 
 

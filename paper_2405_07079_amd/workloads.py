@@ -245,6 +245,23 @@ def random_tiny(seed: int, n: int, granules: int, align: int = 16,
                  np.array([0, n], np.int64), req, dict(seed=seed))
 
 
+def paper_analog(seed: int = 6, n: int = 5_000, lo: int = 1 * KiB, hi: int = 16 * MiB,
+                 p_alloc: float = 0.5, arena: int = 4 * GiB, align: int = 4 * KiB,
+                 algo: int = SEG_FIT) -> Batch:
+    """A stand-in for the paper's evaluation workload (random allocations and
+    frees of blocks between 1 kB and 16 MB, several thousand times): n steps,
+    allocate w.p. p_alloc with a size log-uniform on [lo, hi], else free a
+    uniformly drawn live block; one heap (default: segregated fit over 4 GiB
+    with 4 KiB granules, the setting the paper recommends for device
+    memory)."""
+    rng = heap_rng(seed, 0)
+    sizes = log_uniform_int(rng, n, lo, hi)
+    req = _stream(rng, n, p_alloc, sizes)
+    return Batch("paper_analog", np.array([arena], np.int64), np.array([align], np.int64),
+                 np.array([algo], np.int32), np.array([0, n], np.int64), req,
+                 dict(seed=seed, p_alloc=p_alloc, size_lo=lo, size_hi=hi, steps=n))
+
+
 def max_arena_batch(align: int = 64) -> Batch:
     """Hand-written traces on the largest arena a heap may have, 2^32 - 1
     granules: a block then ends at granule 2^32 - 1 and the whole free arena

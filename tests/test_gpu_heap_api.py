@@ -134,3 +134,25 @@ def test_metadata_budget_admission():
     hda.lib().hda_set_meta_budget(0)
     two.close()
     three.close()
+
+
+def test_paper_analog_trace_matches_oracle():
+    """The per-call harness the benchmark compares with hipMalloc / hipFree:
+    its heap side returns the oracle's results on the stand-in trace."""
+    import ctypes
+    from paper_2405_07079_amd import build as hip_build
+    from paper_2405_07079_amd import workloads as W
+    print("case: paper-analog trace through the call-by-call harness", flush=True)
+    A = ctypes.CDLL(hip_build.ANALOG)
+    vp, i64, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64
+    A.hda_analog_heap.restype = ctypes.c_int
+    A.hda_analog_heap.argtypes = [vp, i64, u64, u64, ctypes.c_int, ctypes.c_uint32, vp, vp]
+    b = W.paper_analog(n=1500)
+    req = np.ascontiguousarray(b.req, np.int64)
+    lat, res = np.zeros(len(req), np.int64), np.zeros(len(req), np.int64)
+    rc = A.hda_analog_heap(req.ctypes.data, len(req), int(b.arena[0]), int(b.align[0]),
+                           int(b.algo[0]), 1024, lat.ctypes.data, res.ctypes.data)
+    assert rc == 0
+    exp, _ = oracle.replay_heap(int(b.algo[0]), int(b.arena[0]), int(b.align[0]), req)
+    assert np.array_equal(res, exp)
+    assert (lat[req >= 0] > 0).all()
