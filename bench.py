@@ -31,6 +31,10 @@ METRIC = ("alloc+free ops/s on 1 MI355X (batched vs per-heap replay); "
           "p50/p99 req latency")
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 BYTES_PER_REQUEST = 16         # 8 B request read + 8 B result written
+# MI355X instruction issue: 256 CUs x 4 SIMDs, 2.4 GHz; a wave64 VALU
+# instruction takes 4 cycles on a 16-lane SIMD; one scalar unit per CU
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
+SALU_ISSUE_PEAK = 256 * 2.4e9
 
 
 def kernel_source_hash():
@@ -67,9 +71,10 @@ def recorded_traffic(algo_names):
     return float(np.mean([t[a] for a in algo_names]))
 
 
-def recorded_lds_conflicts():
-    """LDS bank-conflict cycles per request from the committed instruction-mix
-    summary, while the kernel sources match; else None."""
+def recorded_mix():
+    """Per-request counts from the committed instruction-mix summary, while
+    the kernel sources match: {algorithm: {"valu", "salu", "lds", "branch",
+    "lds_conflict_cycles"}}; else None."""
     path = os.path.join(ROOT, "profiles", "replay_c2_instruction_mix.txt")
     try:
         with open(path) as f:
@@ -78,12 +83,44 @@ def recorded_lds_conflicts():
         return None
     if kernel_source_hash() not in text:
         return None
-    vals = []
+    mix = {}
     for line in text.splitlines():
         parts = line.split()
         if len(parts) == 8 and parts[0] in ("best_fit", "seg_fit"):
-            vals.append(float(parts[7]))
-    return float(np.mean(vals)) if vals else None
+            v = [float(x) for x in parts[1:]]
+            mix[parts[0]] = {"valu": v[0], "salu": v[1], "lds": v[2], "branch": v[3],
+                             "lds_conflict_cycles": v[6]}
+    return mix or None
+
+
+def recorded_lds_conflicts():
+    """LDS bank-conflict cycles per request (mean over the algorithms) from
+    the committed instruction-mix summary, while the kernel sources match."""
+    mix = recorded_mix()
+    if not mix:
+        return None
+    return float(np.mean([m["lds_conflict_cycles"] for m in mix.values()]))
+
+
+def issue_roofline(per_algo_ops):
+    """Instruction issue against the chip's issue rates, from the recorded
+    per-request counts and the measured requests/s: a wave64 VALU
+    instruction holds a 16-lane SIMD for 4 cycles (1,024 SIMDs), and each
+    CU's scalar unit issues one instruction per cycle (256 CUs), at
+    2.4 GHz."""
+    mix = recorded_mix()
+    if not mix:
+        return None
+    out = {"bound": "issue", "unit": "G wave-instructions/s",
+           "peak_valu": VALU_ISSUE_PEAK / 1e9, "peak_salu": SALU_ISSUE_PEAK / 1e9}
+    for name, ops in per_algo_ops.items():
+        if name not in mix:
+            return None
+        m = mix[name]
+        out[name] = {"valu_per_request": m["valu"], "salu_per_request": m["salu"],
+                     "valu_frac": m["valu"] * ops / VALU_ISSUE_PEAK,
+                     "salu_frac": m["salu"] * ops / SALU_ISSUE_PEAK}
+    return out
 
 
 def log(*a):
@@ -477,6 +514,8 @@ def main():
                      # free and live tables stay in VGPRs and LDS for this workload
                      "metadata_hbm_bytes_per_request": 0,
                      "lds_bank_conflict_cycles_per_request": recorded_lds_conflicts(),
+                     # what bounds this kernel: instruction issue (see DESIGN)
+                     "issue": issue_roofline(per_algo),
                      "kernel": f"lean_kernel<{max(resolved['reg_free'], 0)}>",
                      "avg_launch_ms": avg_launch_s * 1e3,
                      "bytes_per_request": BYTES_PER_REQUEST,
