@@ -177,8 +177,8 @@ int hda_replay_per_heap(const hda_batch_desc *d, void *stream);
 int hda_replay_autotune(const hda_batch_desc *d, int32_t sample_heaps, void *stream,
                         hda_tuning *out);
 
-/* One hda_replay call on `d` recorded as a hipGraph (the classify kernel, the
- * per-algorithm launches and their fork/join over the library's streams),
+/* One hda_replay call on `d` recorded as a hipGraph (the classify kernel and
+ * the replay kernel, captured on a private stream),
  * for callers that replay the same descriptor buffers repeatedly: each
  * hda_graph_launch re-runs the whole replay from the heaps' initial state on
  * `stream`, exactly as hda_replay would.  The descriptor's buffers must stay

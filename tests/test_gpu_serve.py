@@ -25,11 +25,11 @@ def server():
 
 
 def test_interleaved_heaps_match_oracle(server):
-    say("case: 8 heaps, interleaved async submits")
+    say("case: 8 heaps (all five algorithms), interleaved async submits")
     rng = np.random.default_rng(3)
     heaps, models, live = [], [], []
     for k in range(8):
-        algo = k % 4
+        algo = k % 5                  # every algorithm, TLSF included
         A = int(rng.integers(64, 4096)) * 256
         heaps.append(server.open(A, 256, algo))
         models.append(oracle.Heap(algo, A, 256))
