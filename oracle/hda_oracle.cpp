@@ -7,7 +7,10 @@
 // free lists with a class-availability bitmap (Sec. III-C, Sec. V-A,
 // Alg. 4-5), and two-level segregated fit (TLSF, Sec. V-B), the same
 // machinery with each power-of-two class split linearly and a two-level
-// bitmap lookup.  No metadata lives in the managed memory: the arena is never
+// bitmap lookup, and the bitmask allocator with a next-fit search (Sec.
+// III-B): one flag per granule, an allocation takes the first run of free
+// granules of the request's length found scanning from where the last one
+// ended.  No metadata lives in the managed memory: the arena is never
 // touched, only described.
 //
 // Only the test-suite, the smoke check and the CPU-baseline leg of the
@@ -54,6 +57,16 @@
 //    fl' > fl and that level's lowest sub-class.  Lists, splitting, merging
 //    and pushing are those of segregated fit; a first-level bit is set
 //    exactly when one of its sub-class lists is non-empty.
+//  * Bitmask allocator (Sec. III-B; the search is next fit, as the paper
+//    suggests): a rover (byte address), 0 at start, set to p + s after allocating
+//    [p, p + s).  An allocation of s granules takes the lowest p >= rover
+//    such that granules [p, p + s) are all free, else the lowest p >= 0
+//    such that they are (wrapping once); on failure the rover stays.  Unlike
+//    the list-based next fit it may cut the run from the middle of a free
+//    block (the scan starts at the rover, not at the block's start).  Free
+//    sets the granules' flags back, so merging is implicit.  The free flags
+//    are kept here as the address-ordered list of maximal free runs, which
+//    is exactly what the flags describe and what the state dump lists.
 //  * No allocation ever fails with an error: a request nothing can satisfy
 //    returns -1 and leaves the state (and the rover) unchanged.
 //  * Partial deallocation (Sec. II-A, Alg. 2) is defined for the sequential
@@ -80,7 +93,7 @@
 
 namespace {
 
-constexpr int FF = 0, NF = 1, BF = 2, SF = 3, TLSF = 4;
+constexpr int FF = 0, NF = 1, BF = 2, SF = 3, TLSF = 4, BITMAP = 5;
 constexpr int SLI = 5, NSL = 1 << SLI;   // TLSF second level: 32 sub-classes
 constexpr int64_t NIL = -1;
 constexpr int E_INVAL = -2, E_BADFREE = -3;
@@ -215,7 +228,7 @@ struct Heap {
         int64_t s = (req + g - 1) / g * g;
         if (s == 0) s = g;
         if (s > A) return -1;
-        int64_t a = segregated() ? alloc_sf(s) : alloc_seq(s);
+        int64_t a = segregated() ? alloc_sf(s) : algo == BITMAP ? alloc_bitmap(s) : alloc_seq(s);
         if (a >= 0) { used[a] = s; live.push_back(a); }
         return a;
     }
@@ -252,6 +265,29 @@ struct Heap {
         if (bsize > s) fl[a + s] = bsize - s;
         if (algo == NF) rover = a + s;
         return a;
+    }
+
+    // Sec. III-B: a run of s free granules, scanning from the rover, then
+    // from the start.
+    int64_t alloc_bitmap(int64_t s) {
+        auto pick = fl.end();
+        int64_t p = -1;
+        for (auto it = fl.begin(); it != fl.end() && pick == fl.end(); ++it) {
+            ++examined;
+            int64_t from = std::max(it->first, rover);
+            if (from + s <= it->first + it->second) { pick = it; p = from; }
+        }
+        for (auto it = fl.begin(); it != fl.end() && pick == fl.end(); ++it) {
+            ++examined;
+            if (it->second >= s) { pick = it; p = it->first; }
+        }
+        if (pick == fl.end()) return -1;
+        int64_t a = pick->first, end = a + pick->second;
+        fl.erase(pick);
+        if (p > a) fl[a] = p - a;
+        if (p + s < end) fl[p + s] = end - (p + s);
+        rover = p + s;
+        return p;
     }
 
     int64_t alloc_sf(int64_t s) {
@@ -366,7 +402,7 @@ struct Heap {
         for (auto& p : fb) { o.push_back(p.first); o.push_back(p.second); }
         o.push_back(int64_t(live.size()));
         for (int64_t a : live) { o.push_back(a); o.push_back(used.at(a)); }
-        o.push_back(algo == NF ? rover : -1);
+        o.push_back(algo == NF || algo == BITMAP ? rover : -1);
         o.push_back(segregated() ? int64_t(bitmap) : 0);
         if (segregated()) {
             for (int c = 0; c < int(head.size()); ++c) {
@@ -381,7 +417,7 @@ struct Heap {
 };
 
 bool valid_params(int algo, int64_t arena, int64_t align) {
-    if (algo < 0 || algo > 4) return false;
+    if (algo < 0 || algo > 5) return false;
     if (align <= 0 || (align & (align - 1))) return false;
     if (arena <= 0 || arena % align) return false;
     if (arena / align >= (int64_t(1) << 32)) return false;

@@ -22,7 +22,7 @@ from __future__ import annotations
 
 import bisect
 
-FIRST_FIT, NEXT_FIT, BEST_FIT, SEG_FIT, TLSF = 0, 1, 2, 3, 4
+FIRST_FIT, NEXT_FIT, BEST_FIT, SEG_FIT, TLSF, BITMAP = 0, 1, 2, 3, 4, 5
 
 # class lower bounds, scaled by 32 so that the TLSF ones are integers
 SF_BOUNDS = [(1 << k) * 32 for k in range(64)]
@@ -53,7 +53,7 @@ class BitmapHeap:
     """First / next / best fit on a granule bitmap (True = free)."""
 
     def __init__(self, algo: int, arena: int, align: int):
-        assert algo in (FIRST_FIT, NEXT_FIT, BEST_FIT)
+        assert algo in (FIRST_FIT, NEXT_FIT, BEST_FIT, BITMAP)
         self.algo, self.g, self.n = algo, align, arena // align
         self.bits = [True] * self.n
         self.rover = 0                   # granule index
@@ -64,6 +64,19 @@ class BitmapHeap:
         if req > self.n * self.g:
             return -1
         s = granules(req, self.g)
+        if self.algo == BITMAP:
+            # Sec. III-B with a next-fit search: the first s free flags in a
+            # row, scanning from the rover bit, then from bit 0
+            starts = list(range(self.rover, self.n - s + 1)) + list(range(0, self.n - s + 1))
+            a = next((p for p in starts if all(self.bits[p:p + s])), None)
+            if a is None:
+                return -1
+            for i in range(a, a + s):
+                self.bits[i] = False
+            self.rover = a + s
+            self.used[a] = s
+            self.live.append(a * self.g)
+            return a * self.g
         fits = [(a, l) for a, l in runs(self.bits) if l >= s]
         if not fits:
             return -1
@@ -117,7 +130,7 @@ class BitmapHeap:
         g = self.g
         return dict(free=[(a * g, l * g) for a, l in runs(self.bits)],
                     live=[(a, self.used[a // g] * g) for a in self.live],
-                    rover=self.rover * g if self.algo == NEXT_FIT else -1,
+                    rover=self.rover * g if self.algo in (NEXT_FIT, BITMAP) else -1,
                     bitmap=0, lists=None)
 
 

@@ -67,11 +67,19 @@ MUTANTS = [
     ("tlsf_fl_bit_not_cleared",
      "if (sl_bitmap[c / NSL] == 0) bitmap &= ~(uint64_t(1) << (c / NSL));", "", 0, "tlsf"),
     ("tlsf_sub_class_from_low_bits", "(b >> (fl - SLI)) - NSL", "(b & (NSL - 1))", 0, "tlsf"),
+    # bitmask allocator (checked by its own pin file)
+    ("bm_from_block_start", "int64_t from = std::max(it->first, rover);",
+     "int64_t from = it->first;", 0, "bitmap"),
+    ("bm_no_wrap", "if (it->second >= s) { pick = it; p = it->first; }", "", 0, "bitmap"),
+    ("bm_left_part_dropped", "if (p > a) fl[a] = p - a;", "", 0, "bitmap"),
+    ("bm_rover_at_start", "rover = p + s;\n        return p;", "rover = p;\n        return p;", 0,
+     "bitmap"),
 ]
 
 PINS = {"seq": [os.path.join(ROOT, "tests", f)
                 for f in ("test_oracle_pins.py", "test_oracle_partial.py")],
-        "tlsf": [os.path.join(ROOT, "tests", "test_oracle_tlsf.py")]}
+        "tlsf": [os.path.join(ROOT, "tests", "test_oracle_tlsf.py")],
+        "bitmap": [os.path.join(ROOT, "tests", "test_oracle_bitmap.py")]}
 
 
 def _replace_nth(text, old, new, n):

@@ -363,7 +363,7 @@ def test_next_fit_resumes_at_rover():
 # ---------------------------------------------------------------------------
 
 def test_bad_params_rejected():
-    for algo, A, g in ((5, 1024, 16), (0, 1024, 24), (0, 1000, 16), (0, 0, 16),
+    for algo, A, g in ((6, 1024, 16), (0, 1024, 24), (0, 1000, 16), (0, 0, 16),
                        (0, 1 << 36, 16)):
         with pytest.raises(ValueError):
             oracle.Heap(algo, A, g)
