@@ -43,6 +43,12 @@ enum {
                         up to the next sub-class bound and served from the
                         first non-empty class at or above it (two-level
                         bitmap lookup); lists as in segregated fit          */
+  HDA_BITMAP = 5     /* bitmask allocator (Sec. III-B): one flag per granule;
+                        an allocation takes the first run of free granules
+                        found scanning from the rover (the end of the last
+                        allocation), else from granule 0.  Replayed only by
+                        hda_bitmap_replay; its state lists the free runs and
+                        the rover as for next fit                           */
 };
 
 /* Status codes. */
@@ -141,6 +147,18 @@ typedef struct hda_batch_desc {
   size_t workspace_bytes;
   hda_tuning tuning;
 } hda_batch_desc;
+
+/* Bitmask-allocator replay (Sec. III-B): every heap of `d` must be
+ * HDA_BITMAP with arena / align <= max_granules (< 2^32); other heaps get
+ * HDA_E_INVAL as status and as every result.  One wavefront per heap scans
+ * 64 words of flags (4,096 granules) per step.  Requests, results, states
+ * and statuses as for hda_replay (partial frees included; the live table
+ * holds meta_live entries, HDA_E_NOMETA past it; meta_free is not used).
+ * The workspace holds each wave's flags and live table:
+ * hda_bitmap_workspace(d, max_granules) bytes (0 on invalid arguments).
+ * Asynchronous on `stream`; HDA_E_RANGE if the workspace is too small. */
+size_t hda_bitmap_workspace(const hda_batch_desc *d, uint64_t max_granules);
+int hda_bitmap_replay(const hda_batch_desc *d, uint64_t max_granules, void *stream);
 
 /* Bytes of device scratch hda_replay needs for `d` (reads only n_heaps,
  * meta_free, meta_live and tuning).  Returns 0 on invalid arguments. */

@@ -50,7 +50,7 @@ namespace hda {
 constexpr uint32_t kNone = 0xffffffffu;
 constexpr int64_t kFail = -1, kEInval = -2, kEBadFree = -3, kENoMeta = -4,
                   kERange = -7;
-enum : int { kFirstFit = 0, kNextFit = 1, kBestFit = 2, kSegFit = 3, kTlsf = 4 };
+enum : int { kFirstFit = 0, kNextFit = 1, kBestFit = 2, kSegFit = 3, kTlsf = 4, kBitmap = 5 };
 
 // Wave-wide minimum of a u32; every lane must be active.  Row-local
 // Hillis-Steele steps with DPP row shifts (identity shifted in) leave each

@@ -169,7 +169,8 @@ __global__ void __launch_bounds__(1024) lean_kernel(ReplayParams p) {
       case kNextFit: lean_one_heap<kNextFit, RF>(p, lds, c, heap); break;
       case kBestFit: lean_one_heap<kBestFit, RF>(p, lds, c, heap); break;
       case kSegFit: lean_one_heap<kSegFit, RF>(p, lds, c, heap); break;
-      default: lean_one_heap<kTlsf, RF>(p, lds, c, heap); break;
+      case kTlsf: lean_one_heap<kTlsf, RF>(p, lds, c, heap); break;
+      default: reject_heap(p, heap); break;  // the bitmask allocator has its own kernel
     }
   });
 }

@@ -4,6 +4,7 @@
 #pragma once
 #include <stdint.h>
 
+#include "hda_bitmap.h"
 #include "hda_core.h"
 #include "hda_lean.h"
 
@@ -42,7 +43,7 @@ struct ReplayParams {
 __device__ __forceinline__ bool heap_params(const ReplayParams& p, int64_t heap, HeapRegs& h) {
   const int64_t A = p.arena[heap], g = p.align[heap];
   const int algo = p.algo[heap];
-  if (algo < 0 || algo > kTlsf || g <= 0 || (g & (g - 1)) || A <= 0 || (A % g) ||
+  if (algo < 0 || algo > kBitmap || g <= 0 || (g & (g - 1)) || A <= 0 || (A % g) ||
       (A / g) >= (int64_t(1) << 32))
     return false;
   h.algo = algo;
@@ -223,8 +224,26 @@ __device__ void replay_any_heap(const ReplayParams& p, const Cold& c, int64_t he
     case kNextFit: replay_heap<kNextFit, RF, RL>(p, c, h, heap); break;
     case kBestFit: replay_heap<kBestFit, RF, RL>(p, c, h, heap); break;
     case kSegFit: replay_heap<kSegFit, RF, RL>(p, c, h, heap); break;
-    default: replay_heap<kTlsf, RF, RL>(p, c, h, heap); break;
+    case kTlsf: replay_heap<kTlsf, RF, RL>(p, c, h, heap); break;
+    default: reject_heap(p, heap); break;  // the bitmask allocator has its own kernel
   }
+}
+
+// Bitmask-allocator replay of one heap (hda_bitmap.h) in a workspace slot
+// of max_granules flags and p.cap_live live entries; a heap of another
+// algorithm or a larger arena is rejected.
+__device__ __forceinline__ void bitmap_one_heap(const ReplayParams& p, uint64_t* bits, Ent* live,
+                                                uint64_t max_granules, int64_t heap) {
+  HeapRegs h;
+  if (!heap_params(p, heap, h) || h.algo != kBitmap || (uint64_t)h.ag > max_granules) {
+    reject_heap(p, heap);
+    return;
+  }
+  BitHeap w(bits, live, h, p.cap_live);
+  w.init();
+  int32_t st = 0;
+  run_requests<kBitmap>(p, w, p.req_off[heap], p.req_off[heap + 1], h.shift, h.arena, st);
+  finish_heap(p, w, heap, st);
 }
 
 }  // namespace hda

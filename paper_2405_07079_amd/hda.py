@@ -16,7 +16,7 @@ import numpy as np
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libhda.so")
 
-FIRST_FIT, NEXT_FIT, BEST_FIT, SEG_FIT, TLSF = 0, 1, 2, 3, 4
+FIRST_FIT, NEXT_FIT, BEST_FIT, SEG_FIT, TLSF, BITMAP = 0, 1, 2, 3, 4, 5
 HDA_OK, HDA_FAIL, HDA_E_INVAL, HDA_E_BADFREE = 0, -1, -2, -3
 HDA_E_NOMETA, HDA_E_DEVICE, HDA_E_BUSY, HDA_E_RANGE = -4, -5, -6, -7
 
@@ -96,7 +96,8 @@ _lib = None
 
 EXPORTS = ["hda_replay_workspace", "hda_replay_resolve", "hda_replay",
            "hda_replay_per_heap", "hda_replay_autotune", "hda_replay_capture",
-           "hda_graph_launch", "hda_graph_destroy", "hda_heap_create", "hda_heap_destroy", "hda_alloc",
+           "hda_graph_launch", "hda_graph_destroy", "hda_bitmap_workspace", "hda_bitmap_replay",
+           "hda_heap_create", "hda_heap_destroy", "hda_alloc",
            "hda_free", "hda_free_partial", "hda_heap_state", "hda_set_meta_budget", "hda_strerror",
            "hda_serve_start", "hda_serve_open", "hda_serve_submit", "hda_serve_poll",
            "hda_serve_wait", "hda_serve_close", "hda_serve_stop", "hda_serve_load"]
@@ -114,6 +115,10 @@ def lib():
         D = ctypes.POINTER(hda_batch_desc)
         L.hda_replay_workspace.restype = ctypes.c_size_t
         L.hda_replay_workspace.argtypes = [D]
+        L.hda_bitmap_workspace.restype = ctypes.c_size_t
+        L.hda_bitmap_workspace.argtypes = [D, ctypes.c_uint64]
+        L.hda_bitmap_replay.restype = ctypes.c_int
+        L.hda_bitmap_replay.argtypes = [D, ctypes.c_uint64, vp]
         L.hda_replay_resolve.restype = ctypes.c_int
         L.hda_replay_resolve.argtypes = [D, ctypes.POINTER(hda_tuning)]
         L.hda_replay.restype = ctypes.c_int
@@ -293,6 +298,29 @@ def hda_replay_resolve(db: DeviceBatch) -> dict:
 def hda_replay(db: DeviceBatch, stream=None) -> None:
     """Enqueue the batched replay on `stream` (default: torch's current)."""
     _check(lib().hda_replay(ctypes.byref(db.desc()), _stream_ptr(stream)), "hda_replay")
+
+
+def max_granules(batch) -> int:
+    """The largest arena of a workloads.Batch in granules."""
+    return int((np.asarray(batch.arena) // np.asarray(batch.align)).max()) if batch.heaps else 1
+
+
+def hda_bitmap_replay(db: DeviceBatch, max_gran: int, stream=None) -> None:
+    """Enqueue the bitmask-allocator replay (every heap HDA_BITMAP, arenas of
+    at most `max_gran` granules) on `stream`; the batch gets a workspace of
+    hda_bitmap_workspace bytes the first time."""
+    import torch
+    d = db.desc()
+    n = lib().hda_bitmap_workspace(ctypes.byref(d), int(max_gran))
+    if n == 0:
+        raise HdaError(HDA_E_INVAL, "hda_bitmap_workspace")
+    ws = getattr(db, "bitmap_ws", None)
+    if ws is None or ws.numel() < n:
+        ws = torch.empty(n, dtype=torch.uint8, device=db.res.device)
+        db.bitmap_ws = ws
+    d.workspace, d.workspace_bytes = ws.data_ptr(), ws.numel()
+    _check(lib().hda_bitmap_replay(ctypes.byref(d), int(max_gran), _stream_ptr(stream)),
+           "hda_bitmap_replay")
 
 
 def hda_replay_per_heap(db: DeviceBatch, stream=None) -> None:

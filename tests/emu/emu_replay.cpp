@@ -27,6 +27,9 @@ struct LaneJob {
   int64_t heap;
   int shape;
   int done;
+  uint64_t* bits;        // bitmask allocator: flags and live table
+  Ent* live;
+  uint64_t max_granules;
 };
 LaneJob g_job;
 
@@ -47,7 +50,10 @@ void lane_main() {
     case 1: replay_any_heap<1, 2>(*g_job.p, *g_job.c, g_job.heap); break;
     case 2: replay_any_heap<4, 8>(*g_job.p, *g_job.c, g_job.heap); break;
     case 3: lean_any<1>(*g_job.p, *g_job.lds, *g_job.c, g_job.heap); break;
-    default: lean_any<4>(*g_job.p, *g_job.lds, *g_job.c, g_job.heap); break;
+    case 4: lean_any<4>(*g_job.p, *g_job.lds, *g_job.c, g_job.heap); break;
+    default:
+      bitmap_one_heap(*g_job.p, g_job.bits, g_job.live, g_job.max_granules, g_job.heap);
+      break;
   }
   // a finished lane keeps handing over until every lane has finished
   g_job.done++;
@@ -61,7 +67,7 @@ void lane_main() {
   }
 }
 
-const int kShapeRF[] = {0, 1, 4, 0, 0}, kShapeRL[] = {0, 2, 8, 0, 0};
+const int kShapeRF[] = {0, 1, 4, 0, 0, 0}, kShapeRL[] = {0, 2, 8, 0, 0, 0};
 
 // Run one heap as a wave of 64 fibers.
 void run_wave(EmuWave& w, std::vector<std::vector<uint8_t>>& stacks) {
@@ -82,8 +88,9 @@ void run_wave(EmuWave& w, std::vector<std::vector<uint8_t>>& stacks) {
 // shape: general core with 0 = no register part, 1 = (1, 2) chunks, 2 = (4, 8)
 // chunks in registers; lean core with 3 = one, 4 = four free chunks in
 // registers, where a heap that outgrows its tiers moves to the general core
-// on the same "LDS" plus spill tables (overflowed[h] = 1).  kf/kl: entries in
-// "LDS"; cap_free/cap_live: capacities.
+// on the same "LDS" plus spill tables (overflowed[h] = 1); 5 = the bitmask
+// allocator (flags for the heap's own granules, cap_live live entries).
+// kf/kl: entries in "LDS"; cap_free/cap_live: capacities.
 extern "C" int emu_replay(int64_t H, const int64_t* arena, const int64_t* align,
                           const int32_t* algo, const int64_t* req_off, const int64_t* req,
                           int64_t* res, int64_t* state, const int64_t* state_off,
@@ -95,7 +102,7 @@ extern "C" int emu_replay(int64_t H, const int64_t* arena, const int64_t* align,
   p.arena = arena; p.align = align; p.algo = algo; p.req_off = req_off; p.req = req;
   p.res = res; p.state = state; p.state_off = state_off; p.state_len = state_len;
   p.status = status;
-  const bool lean = shape >= 3;
+  const bool lean = shape == 3 || shape == 4;
   // lean core: an LDS pool with room for kf 16-byte free and kl live entries;
   // the general core it may move to has no LDS part
   const uint32_t pool = kf * 16u + kl * 8u;
@@ -139,6 +146,14 @@ extern "C" int emu_replay(int64_t H, const int64_t* arena, const int64_t* align,
       run_wave(w, stacks);
       n_sync = w.syncs;
       if (overflowed) overflowed[h] = migrated != before;
+    } else if (shape == 5) {
+      // poisoned flags past the heap's words and a poisoned live table
+      const uint64_t ag = (align[h] > 0 && arena[h] > 0) ? uint64_t(arena[h] / align[h]) : 1u;
+      std::vector<uint64_t> bits((ag + 63u) / 64u + 1u, 0xA5A5A5A5A5A5A5A5ull);
+      std::vector<Ent> live(size_t(cap_live) + 1u, 0xA5A5A5A5A5A5A5A5ull);
+      g_job = LaneJob{&p, &c, nullptr, h, shape, 0, bits.data(), live.data(), ag};
+      run_wave(w, stacks);
+      n_sync = w.syncs;
     } else {
       g_job = LaneJob{&p, &c, nullptr, h, shape, 0};
       run_wave(w, stacks);

@@ -222,3 +222,46 @@ def test_partial_frees_random_small_heaps():
     for shape in (1, 3):
         res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=512, cl=512, shape=shape)
         check(b, res, states, status)
+
+
+# ---- the bitmask allocator (one flag per granule, next-fit scan) ----
+
+def test_bitmap_random_small_heaps():
+    rng = np.random.default_rng(21)
+    parts = []
+    for h in range(40):
+        gran = int(rng.integers(1, 700))       # ragged word counts
+        parts.append(W.random_tiny(int(rng.integers(1 << 30)), int(rng.integers(0, 300)),
+                                   gran, align=int(1 << rng.integers(0, 8)), algo=5,
+                                   max_granules=max(1, gran // int(rng.integers(1, 6))),
+                                   p_partial=float(rng.uniform(0, 0.6))))
+    b = W.concat(parts)
+    res, states, status, _ = emu.replay(b, cf=1024, cl=1024, shape=5)
+    check(b, res, states, status)
+
+
+@pytest.mark.parametrize("granules,hi", ((5000, 200), (9000, 9000), (70_000, 3000)))
+def test_bitmap_runs_across_words_and_steps(granules, hi):
+    """Arenas of several 4,096-granule scan steps and runs longer than a word
+    or a step."""
+    b = W.random_tiny(granules, 600, granules, align=16, algo=5, max_granules=hi,
+                      p_partial=0.2)
+    res, states, status, _ = emu.replay(b, cf=4096, cl=4096, shape=5)
+    check(b, res, states, status)
+
+
+def test_bitmap_16MiB_heap():
+    b = W.uniform_batch(heaps=1, n=1500, algo=5)
+    res, states, status, _ = emu.replay(b, cf=4096, cl=4096, shape=5)
+    check(b, res, states, status)
+
+
+def test_bitmap_live_capacity():
+    """A live table too small: E_NOMETA, results equal to the oracle's up to
+    the first refusal."""
+    b = W.random_tiny(3, 400, 256, align=16, p_alloc=0.8, algo=5, max_granules=4)
+    res, states, status, _ = emu.replay(b, cf=4096, cl=16, shape=5)
+    assert status[0] == -4
+    ores, _ = oracle.replay_heap(5, int(b.arena[0]), int(b.align[0]), b.req)
+    k = int(np.nonzero(res == -4)[0][0])
+    assert np.array_equal(res[:k], ores[:k])
