@@ -249,6 +249,8 @@ def main():
                          "(0 = default, -1 = none)")
     ap.add_argument("--no-paper-analog", action="store_true",
                     help="skip the per-call comparison with hipMalloc / hipFree")
+    ap.add_argument("--no-bitmap", action="store_true",
+                    help="skip the leg that replays the batch with the bitmask allocator")
     ap.add_argument("--no-tlsf", action="store_true",
                     help="skip the leg that replays the batch with two-level segregated fit")
     ap.add_argument("--partial-frees", type=float, default=0.02,
@@ -376,6 +378,34 @@ def main():
         del tdb
         log(f"[bench] tlsf: {tlsf['value'] / 1e9:.3f} G ops/s")
 
+    bitmap = None
+    if not args.no_bitmap:
+        # the same batch replayed by the bitmask allocator (Sec. III-B): one
+        # flag per granule, next-fit scan, its own kernel
+        bb = batch.with_algo(W.BITMAP)
+        bdb = hda.upload(bb, share=dbs[algos[0]])
+        mg = hda.max_granules(bb)
+        hda.hda_bitmap_replay(bdb, mg, stream)
+        torch.cuda.synchronize()
+        if int((bdb.status != 0).sum().item()):
+            raise RuntimeError("bitmap leg: heaps reported errors")
+        bms = []
+        for _ in range(max(1, min(args.steps, 3))):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            hda.hda_bitmap_replay(bdb, mg, stream)
+            e1.record(stream)
+            bms.append((e0, e1))
+        torch.cuda.synchronize()
+        bms = [a.elapsed_time(b) for a, b in bms]
+        bitmap = {"workload": "the batch above replayed by the bitmask allocator (one flag "
+                              "per granule, 32 KiB per heap; next-fit scan from the rover)",
+                  "value": batch.requests / (float(np.median(bms)) / 1e3), "unit": "ops/s",
+                  "launch_ms": float(np.median(bms))}
+        del bdb
+        log(f"[bench] bitmap: {bitmap['value'] / 1e9:.3f} G ops/s")
+
     partial = None
     if args.partial_frees > 0:
         # the same batch shape on best fit, with that fraction of the frees
@@ -458,6 +488,15 @@ def main():
                          f"{csub.requests * len(algos)} requests, {ct:.1f} s wall "
                          f"on {cores} threads"}
         log(f"[bench] cpu oracle: {cpu['value'] / 1e6:.2f} M ops/s on {cores} threads")
+        if bitmap is not None:
+            bsub = csub.with_algo(W.BITMAP)
+            t1 = time.perf_counter()
+            oracle.replay_batch(bsub, threads=cores, want_state=True)
+            bt = time.perf_counter() - t1
+            bitmap["cpu_baseline"] = {"value": bsub.requests / bt, "unit": "ops/s",
+                                      "cores": cores, "kind": "oracle",
+                                      "sample": f"first {bsub.heaps} heaps, {bsub.requests} "
+                                                f"requests, {bt:.1f} s wall"}
         if tlsf is not None:
             tsub = csub.with_algo(W.TLSF)
             t1 = time.perf_counter()
@@ -521,6 +560,7 @@ def main():
                      "bytes_per_request": BYTES_PER_REQUEST,
                      "requests_per_launch": batch.requests},
         "tlsf": tlsf,
+        "bitmap": bitmap,
         "partial_free": partial,
         "paper_analog": analog,
         "serving": serving,

@@ -33,6 +33,10 @@ FIRST_FIT, NEXT_FIT, BEST_FIT, SEG_FIT, TLSF = 0, 1, 2, 3, 4
 ALGO_NAMES = {FIRST_FIT: "first_fit", NEXT_FIT: "next_fit",
               BEST_FIT: "best_fit", SEG_FIT: "seg_fit", TLSF: "tlsf"}
 
+# the bitmask allocator (Sec. III-B) has its own replay entry point and is
+# not among the algorithms above, which the table-based replay serves
+BITMAP = 5
+
 KiB, MiB, GiB = 1 << 10, 1 << 20, 1 << 30
 
 
@@ -60,7 +64,8 @@ class Batch:
 
     def with_algo(self, algo: int) -> "Batch":
         """Same streams, every heap switched to ``algo``."""
-        return Batch(f"{self.name}/{ALGO_NAMES[algo]}", self.arena, self.align,
+        name = ALGO_NAMES.get(algo, "bitmap" if algo == BITMAP else str(algo))
+        return Batch(f"{self.name}/{name}", self.arena, self.align,
                      np.full_like(self.algo, algo), self.req_off, self.req,
                      dict(self.meta))
 

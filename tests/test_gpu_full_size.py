@@ -5,7 +5,8 @@ on properties that hold at any size).
 * 4,096 heaps x 100,000 requests (16 MiB arenas), best fit, segregated
   fit and TLSF, default tuning, states dumped: 24 sampled heaps per algorithm
   (including the first and the last) compared element by element.
-* The same batch on best fit with 2 % of the frees partial: 24 sampled heaps.
+* The same batch on best fit with 2 % of the frees partial, and replayed by
+  the bitmask allocator: 24 sampled heaps each.
 * The uneven batch (16,384 heaps, 46.9 M requests), autotuned and launched
   as a captured graph: 48 sampled heaps plus the 4 longest.
 * The service under 1e7 requests/s from 100,000 clients (one heap each):
@@ -60,6 +61,25 @@ def test_4096_heaps_full_size_sampled(c2, algo):
     heaps = sorted(set(rng.choice(b.heaps, 22, replace=False).tolist()) | {0, b.heaps - 1})
     res = np.empty(b.requests, np.int64)
     for h in heaps:   # copy only the sampled heaps' results back
+        a, e = int(b.req_off[h]), int(b.req_off[h + 1])
+        res[a:e] = db.res[a:e].cpu().numpy()
+    check_heaps(b, res, db, status, heaps)
+
+
+def test_4096_heaps_bitmap_full_size_sampled(c2):
+    """The benchmark's bitmask-allocator leg: the same batch, one flag per
+    granule; 24 sampled heaps element by element."""
+    b = c2.with_algo(W.BITMAP)
+    say("case: 4096 x 16 MiB heaps, 100k requests each, bitmask allocator")
+    db = hda.upload(b)
+    hda.hda_bitmap_replay(db, hda.max_granules(b))
+    torch.cuda.synchronize()
+    status = db.status.cpu().numpy()
+    assert (status == 0).all()
+    rng = np.random.default_rng(55)
+    heaps = sorted(set(rng.choice(b.heaps, 22, replace=False).tolist()) | {0, b.heaps - 1})
+    res = np.empty(b.requests, np.int64)
+    for h in heaps:
         a, e = int(b.req_off[h]), int(b.req_off[h + 1])
         res[a:e] = db.res[a:e].cpu().numpy()
     check_heaps(b, res, db, status, heaps)
