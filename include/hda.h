@@ -38,7 +38,7 @@ enum {
   HDA_NEXT_FIT = 1,  /* first fit resumed at a rover (Sec. II-A, Sec. IV)    */
   HDA_BEST_FIT = 2,  /* smallest block >= s, lowest address on ties (Alg. 3) */
   HDA_SEG_FIT = 3,   /* power-of-two classes + bitmap, LIFO lists (Alg. 4-5) */
-  HDA_TLSF = 4       /* two-level segregated fit (Sec. V-B): each power of two
+  HDA_TLSF = 4,      /* two-level segregated fit (Sec. V-B): each power of two
                         split into 32 linear sub-classes; a request is rounded
                         up to the next sub-class bound and served from the
                         first non-empty class at or above it (two-level

@@ -80,11 +80,13 @@ struct BitHeap {
     rover = 0;
   }
 
-  // The lowest p >= lo with granules [p, p + s) all free, or kNone.
-  __device__ uint32_t find(uint32_t lo, uint32_t s) const {
+  // The lowest p >= lo with granules [p, p + s) all free, or kNone.  A run
+  // is detected in the step holding its granule p + s - 1, so only starts
+  // below `below_end` are wanted once steps begin at or past below_end + s.
+  __device__ uint32_t find(uint32_t lo, uint32_t s, uint64_t below_end = 1ull << 40) const {
     const uint32_t lane = lane_id();
     uint64_t carry = 0;  // free granules in a row ending just below the step
-    for (uint32_t w0 = lo >> 6; w0 < nw; w0 += 64u) {
+    for (uint32_t w0 = lo >> 6; w0 < nw && 64ull * w0 < below_end + s; w0 += 64u) {
       const uint32_t wi = w0 + lane;
       const uint64_t below = wi == (lo >> 6) ? (1ull << (lo & 63u)) - 1ull : 0ull;
       const uint64_t w = load(wi) & ~below;
@@ -141,7 +143,8 @@ struct BitHeap {
   __device__ int64_t alloc(uint32_t sg, uint32_t) {
     if (sg > ag) return kFail;
     uint32_t p = find(rover, sg);
-    if (p == kNone) p = find(0u, sg);
+    // wrapping: starts at or past the rover were all tried
+    if (p == kNone) p = find(0u, sg, rover);
     if (p == kNone) return kFail;
     if (L >= capL) return kENoMeta;
     mark(p, sg, false);

@@ -35,3 +35,11 @@ def test_binding_knows_every_symbol():
 def test_strerror_without_gpu():
     assert hda.strerror(hda.HDA_E_BADFREE).startswith("free of an offset")
     assert hda.strerror(12345) == "unknown error"
+
+
+def test_header_compiles_as_c_and_cpp():
+    """include/hda.h stands alone for C and C++ callers."""
+    import subprocess
+    hdr = os.path.join(ROOT, "include", "hda.h")
+    for lang, cc in (("c", "gcc"), ("c++", "g++")):
+        subprocess.check_call([cc, "-fsyntax-only", "-Wall", "-Werror", "-x", lang, hdr])
