@@ -306,14 +306,18 @@ struct LeanHeap {
       // smallest size, then lowest address; keyed by the leftover es - sg,
       // which (sg >= 1) never equals kNone, as a whole-arena size of
       // 2^32 - 1 granules would
-      uint32_t bs = kNone, ba = kNone, bc = 0;
+      // (leftover, address) compared as one 64-bit value: one vector compare
+      // per chunk, no mask logic on the scalar unit
+      uint64_t best = ~0ull;
+      uint32_t bc = 0;
       scan([&](uint32_t c, uint32_t ea, uint32_t es, uint32_t) {
         const uint32_t t = es >= sg ? es - sg : kNone;
-        const bool take = t < bs || (t == bs && ea < ba);
-        bs = take ? t : bs;
-        ba = take ? ea : ba;
+        const uint64_t key = ((uint64_t)t << 32) | ea;
+        const bool take = key < best;
+        best = take ? key : best;
         bc = take ? c : bc;
       });
+      const uint32_t bs = (uint32_t)(best >> 32), ba = (uint32_t)best;
       const uint32_t K = wave_min(bs);
       if (K == kNone) return false;
       uint64_t mk = ballot(bs == K);
@@ -389,15 +393,14 @@ struct LeanHeap {
     // right neighbour; its own start, which no free block has, stands in for
     // its end so that empty slots (address ~0) do not match.
     const uint32_t xe = x + sz == kNone ? x : x + sz;
-    uint64_t ML = 0ull, MR = 0ull;
+    // chunk + 1 of this lane's left / right neighbour (0: none); there is at
+    // most one of each, so two ballots after the scan find them
     uint32_t cl = 0, cr = 0;
     scan([&](uint32_t c, uint32_t ea, uint32_t es, uint32_t) {
-      const bool il = ea + es == x, ir = ea == xe;
-      ML |= ballot(il);
-      MR |= ballot(ir);
-      cl = il ? c : cl;
-      cr = ir ? c : cr;
+      cl = ea + es == x ? c + 1u : cl;
+      cr = ea == xe ? c + 1u : cr;
     });
+    const uint64_t ML = ballot(cl != 0u), MR = ballot(cr != 0u);
     if ((ML | MR) == 0ull) {
       if (F >= capF) return kENoMeta;
       // (the freed block still counts as live here: the check is on the safe side)
@@ -410,16 +413,16 @@ struct LeanHeap {
       ++F;
       set_room();
     } else if (MR == 0ull) {
-      const uint32_t l = ctz64(ML), jl = 64u * rdlane(cl, l) + l;
+      const uint32_t l = ctz64(ML), jl = 64u * (rdlane(cl, l) - 1u) + l;
       const uint32_t sl = size_at(jl);
       write(jl, x - sl, sl + sz, kSeg ? seg_key(sl + sz) : 0u);
     } else if (ML == 0ull) {
-      const uint32_t l = ctz64(MR), jr = 64u * rdlane(cr, l) + l;
+      const uint32_t l = ctz64(MR), jr = 64u * (rdlane(cr, l) - 1u) + l;
       const uint32_t sr = size_at(jr);
       write(jr, x, sz + sr, kSeg ? seg_key(sz + sr) : 0u);
     } else {
-      const uint32_t ll = ctz64(ML), jl = 64u * rdlane(cl, ll) + ll;
-      const uint32_t lr = ctz64(MR), jr = 64u * rdlane(cr, lr) + lr;
+      const uint32_t ll = ctz64(ML), jl = 64u * (rdlane(cl, ll) - 1u) + ll;
+      const uint32_t lr = ctz64(MR), jr = 64u * (rdlane(cr, lr) - 1u) + lr;
       const uint32_t sl = size_at(jl), sr = size_at(jr), ms = sl + sz + sr;
       const uint32_t last = F - 1u;
       uint32_t keep;  // slot that ends up holding the merged block
