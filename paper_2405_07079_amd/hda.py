@@ -257,7 +257,12 @@ def upload(batch, device="cuda", order="lpt", with_state=True, meta_free=4096,
         order_t = t(order, np.int32)
     state = state_off = state_len = None
     if with_state:
-        blocks = np.minimum(lens + 1, meta_free + meta_live)
+        # a request adds at most one block to the tables -- two for the
+        # bitmask allocator, which may cut from the middle of a free run, and
+        # whose free runs are separated by live blocks
+        blocks = np.where(np.asarray(batch.algo) == BITMAP,
+                          np.minimum(2 * lens + 1, 2 * meta_live + 1),
+                          np.minimum(lens + 1, meta_free + meta_live))
         caps = state_words(batch.algo, blocks).astype(np.int64)
         so = np.zeros(H + 1, np.int64)
         np.cumsum(caps, out=so[1:])
