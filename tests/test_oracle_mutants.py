@@ -118,7 +118,7 @@ def test_every_anchor_is_unique_enough():
 
 def test_pins_catch_planted_mistakes():
     with tempfile.TemporaryDirectory() as tmp:
-        with ThreadPoolExecutor(4) as ex:
+        with ThreadPoolExecutor(max(1, min(8, os.cpu_count() or 1))) as ex:
             results = list(ex.map(lambda m: _run(m, tmp), MUTANTS))
     survivors = [name for name, rc in results if rc == 0]
     assert not survivors, f"pins did not catch: {survivors}"
