@@ -272,12 +272,13 @@ struct LeanHeap {
       // (last in that order) has key ~0, which the scan cannot tell from
       // "none", so it is looked for separately when nothing else fits.
       const uint32_t nr = ~rover;
-      uint32_t best = kNone, bc = 0;
+      uint32_t best = kNone, bc = 0, bsz = 0;  // bsz: the candidate's size
       scan([&](uint32_t c, uint32_t ea, uint32_t es, uint32_t) {
         const uint32_t t = es >= sg ? (ALGO == kFirstFit ? ea : ea + es + nr) : kNone;
         const bool lt = t < best;
         best = lt ? t : best;
         bc = lt ? c : bc;
+        bsz = lt ? es : bsz;
       });
       const uint32_t K = wave_min(best);
       uint64_t mk;
@@ -292,6 +293,7 @@ struct LeanHeap {
           const bool hit = es >= sg && ea + es == rover;
           any |= ballot(hit);
           bc = hit ? c : bc;
+          bsz = hit ? es : bsz;
         });
         if (any == 0ull) return false;
         mk = any;
@@ -299,7 +301,7 @@ struct LeanHeap {
       }
       const uint32_t l = ctz64(mk);
       j = 64u * rdlane(bc, l) + l;
-      s = size_at(j);
+      s = rdlane(bsz, l);
       a = ALGO == kFirstFit ? K : end - s;
       return true;
     } else if constexpr (ALGO == kBestFit) {
@@ -336,19 +338,21 @@ struct LeanHeap {
       // above the request's class
       if (kreq >= kClasses) return false;
       const uint32_t lo = kreq << kKeyShift;
-      uint32_t best = kNone, bc = 0;
-      scan([&](uint32_t ch, uint32_t, uint32_t, uint32_t ek) {
+      uint32_t best = kNone, bc = 0, ba = 0, bsz = 0;  // the candidate's block
+      scan([&](uint32_t ch, uint32_t ea, uint32_t es, uint32_t ek) {
         const uint32_t t = ek >= lo ? ek : kNone;
         const bool lt = t < best;
         best = lt ? t : best;
         bc = lt ? ch : bc;
+        ba = lt ? ea : ba;
+        bsz = lt ? es : bsz;
       });
       const uint32_t K = wave_min(best);
       if (K == kNone) return false;
       const uint32_t l = ctz64(ballot(best == K));
       j = 64u * rdlane(bc, l) + l;
-      uint32_t k;
-      read(j, a, s, k);
+      a = rdlane(ba, l);
+      s = rdlane(bsz, l);
       return true;
     }
   }
