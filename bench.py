@@ -262,7 +262,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); "
+        print(f"bench.py: the replay runs on exactly one GPU (asked for {args.gpus}); "
               "heaps are independent, so N GPUs would each replay their own share "
               "with no communication -- run N=1.", file=sys.stderr)
         return 2
