@@ -6,14 +6,19 @@
 // 0, and moves the rover past them; a free sets the flags back, so merging is
 // implicit.
 //
-// The scan reads 64 words (4,096 granules) per step, one per lane.  For each
-// lane the run of free granules that reaches the bottom of its word from
-// below is found from the nearest lower lane whose word is not all free (a
-// ballot, then a lane permute for that word's top run); a run that reaches
-// s inside a word is found with s-1 shift-and steps.  The lowest start in the
-// step is a wave-wide minimum.  Same rules as the other cores: values that
-// feed a cross-lane operation are computed by all lanes with selects, never
-// under a lane-dependent branch.
+// The flags are summarised per node of 64 words (4,096 granules): the free
+// run at the node's bottom, the free run at its top and the longest free run
+// inside it, kept exact by every change of the flags.  A search reads the
+// words of the rover's node (one word per lane), then the node summaries (one
+// node per lane), which name the first node where a long enough run reaches
+// its s-th granule, then that node's words: three dependent reads where a
+// flag-only scan takes one per 4,096 granules.  Inside a step, the run
+// reaching the bottom of a lane's word (or node) from below is found from the
+// nearest lower lane that is not all free (a ballot, then a lane permute for
+// that lane's top run); a run that reaches s inside a word is found with s-1
+// shift-and steps.  The lowest start in the step is a wave-wide minimum.
+// Same rules as the other cores: values that feed a cross-lane operation are
+// computed by all lanes with selects, never under a lane-dependent branch.
 #pragma once
 #include <stdint.h>
 
@@ -52,21 +57,80 @@ __device__ __forceinline__ uint32_t wave_scan_max(uint32_t v) {
   return v;
 }
 
+// Longest run of set bits in w.  y[k] marks the bits that start a run of at
+// least 2^k; the length is then built from the top power down, keeping the
+// starts that still reach it.
+__device__ __forceinline__ uint32_t longest_run(uint64_t w) {
+  uint64_t y[6];
+  y[0] = w;
+#pragma unroll
+  for (int k = 1; k < 6; ++k) y[k] = y[k - 1] & (y[k - 1] >> (1u << (k - 1)));
+  uint64_t z = ~0ull;  // starts of runs of at least len
+  uint32_t len = 0;
+#pragma unroll
+  for (int k = 5; k >= 0; --k) {
+    const uint64_t t = z & (y[k] >> len);  // len <= 62 here
+    z = t ? t : z;
+    len += t ? (1u << k) : 0u;
+  }
+  return w == ~0ull ? 64u : len;
+}
+
+constexpr uint32_t kNodeGranules = 4096;  // 64 words
+
+// Node summary word: bottom run | top run << 16 | longest run << 32 (each
+// 0..4096 granules).  0 = no free granule.
+__device__ __forceinline__ uint32_t node_low(uint64_t r) { return (uint32_t)r & 0xffffu; }
+__device__ __forceinline__ uint32_t node_top(uint64_t r) { return (uint32_t)(r >> 16) & 0xffffu; }
+__device__ __forceinline__ uint32_t node_max(uint64_t r) { return (uint32_t)(r >> 32); }
+
+// Summary of the node whose word `lane` is w (all lanes).
+__device__ __forceinline__ uint64_t node_summary(uint64_t w) {
+  const uint32_t lane = lane_id();
+  const bool full = w == ~0ull;
+  const uint32_t low1 = full ? 64u : ctz64u(~w);
+  const uint32_t top1 = full ? 64u : clz64u(~w);
+  const uint64_t nf = ballot(!full);
+  const uint64_t lt = nf & ((1ull << lane) - 1ull);
+  const uint32_t ps = lt ? 63u - clz64u(lt) : 0u;
+  const uint32_t tp = shfl(top1, ps);
+  // free run ending just below this word, inside the node
+  const uint32_t pre = lt ? tp + 64u * (lane - 1u - ps) : 64u * lane;
+  const uint32_t topv = full ? pre + 64u : top1;  // free run ending at this word's top
+  uint32_t m = longest_run(w);
+  m = (!full && pre + low1 > m) ? pre + low1 : m;
+  m = (lane == 63u && topv > m) ? topv : m;
+  const uint32_t mx = rdlane(wave_scan_max(m), 63u);
+  const uint32_t fl = nf ? ctz64u(nf) : 0u;
+  const uint32_t lw = rdlane(low1, fl);
+  const uint32_t bottom = nf ? 64u * fl + lw : kNodeGranules;
+  const uint32_t top = rdlane(topv, 63u);
+  return (uint64_t)bottom | ((uint64_t)top << 16) | ((uint64_t)mx << 32);
+}
+
 struct BitHeap {
   HDA_GLOBAL uint64_t* bits;   // nw words: bit i of word w = granule 64 w + i free
+  HDA_GLOBAL uint64_t* nodes;  // nn node summaries, node n = words 64 n .. 64 n + 63
   HDA_GLOBAL Ent* live;        // capL entries
   int64_t arena;
-  uint32_t shift, ag, nw;
+  uint32_t shift, ag, nw, nn;
   uint32_t L, rover, capL;
 
-  __device__ __forceinline__ BitHeap(uint64_t* b, Ent* lv, const HeapRegs& h, uint32_t cap_live)
-      : bits((HDA_GLOBAL uint64_t*)b), live((HDA_GLOBAL Ent*)lv), arena(h.arena),
-        shift(h.shift), ag(h.ag), nw((h.ag + 63u) >> 6), L(0), rover(0), capL(cap_live) {}
+  __device__ __forceinline__ BitHeap(uint64_t* b, uint64_t* nd, Ent* lv, const HeapRegs& h,
+                                     uint32_t cap_live)
+      : bits((HDA_GLOBAL uint64_t*)b), nodes((HDA_GLOBAL uint64_t*)nd),
+        live((HDA_GLOBAL Ent*)lv), arena(h.arena), shift(h.shift), ag(h.ag),
+        nw((h.ag + 63u) >> 6), nn((((h.ag + 63u) >> 6) + 63u) >> 6), L(0), rover(0),
+        capL(cap_live) {}
 
   // word wi, or 0 past the end (the load is clamped, not branched around)
   __device__ __forceinline__ uint64_t load(uint32_t wi) const {
     const uint64_t v = bits[wi < nw ? wi : nw - 1u];
     return wi < nw ? v : 0ull;
+  }
+  __device__ __forceinline__ uint64_t load_node(uint32_t ni) const {
+    const uint64_t v = nodes[ni < nn ? ni : nn - 1u];
+    return ni < nn ? v : 0ull;
   }
 
   // Alg. 6: every granule free.
@@ -76,66 +140,109 @@ struct BitHeap {
       const uint32_t rest = ag - 64u * (wi < nw ? wi : 0u);   // granules from this word on
       if (wi < nw) bits[wi] = rest >= 64u ? ~0ull : (1ull << rest) - 1ull;
     }
+    for (uint32_t n0 = 0; n0 < nn; n0 += 64u) {
+      const uint32_t ni = n0 + lane_id();
+      const uint32_t rest = ag - kNodeGranules * (ni < nn ? ni : 0u);
+      const uint32_t g = rest < kNodeGranules ? rest : kNodeGranules;  // one run [0, g)
+      const uint32_t top = g == kNodeGranules ? g : 0u;
+      if (ni < nn) nodes[ni] = (uint64_t)g | ((uint64_t)top << 16) | ((uint64_t)g << 32);
+    }
     L = 0;
     rover = 0;
   }
 
-  // The lowest p >= lo with granules [p, p + s) all free, or kNone.  A run
-  // is detected in the step holding its granule p + s - 1, so only starts
-  // below `below_end` are wanted once steps begin at or past below_end + s.
+  // One step over node n's 64 words: the lowest p >= lo whose s-th granule
+  // p + s - 1 lies in the node, with `carry` free granules in a row ending
+  // just below the node (granules below lo count as used), or kNone; carry
+  // becomes the free run ending at the node's top.
+  __device__ __forceinline__ uint32_t word_step(uint32_t n, uint32_t lo, uint32_t s,
+                                                uint64_t& carry) const {
+    const uint32_t lane = lane_id();
+    const uint32_t wi = 64u * n + lane;
+    const uint32_t lw = lo >> 6;
+    const uint64_t below = wi < lw ? ~0ull : wi == lw ? (1ull << (lo & 63u)) - 1ull : 0ull;
+    const uint64_t w = load(wi) & ~below;
+    const bool full = w == ~0ull;
+    const uint32_t low1 = full ? 64u : ctz64u(~w);   // free run at the bottom
+    const uint32_t top1 = full ? 64u : clz64u(~w);   // free run at the top
+    const uint64_t lt = ballot(!full) & ((1ull << lane) - 1ull);
+    const uint32_t ps = lt ? 63u - clz64u(lt) : 0u;
+    const uint32_t tp = shfl(top1, ps);
+    const uint64_t pre = lt ? (uint64_t)tp + 64ull * (lane - 1u - ps) : carry + 64ull * lane;
+    const uint64_t base = 64ull * wi;
+    // a run that reaches s in this word, having started below it
+    uint32_t cand = (pre < s && pre + low1 >= s) ? (uint32_t)(base - pre) : kNone;
+    // a run of s inside this word
+    if (s <= 64u) {
+      uint64_t y = w;
+      for (uint32_t k = 1; k < s;) {
+        const uint32_t d = k < s - k ? k : s - k;
+        y &= y >> d;
+        k += d;
+      }
+      const uint32_t in = y ? (uint32_t)base + ctz64u(y) : kNone;
+      cand = in < cand ? in : cand;
+    }
+    const uint64_t topv = full ? pre + 64ull : (uint64_t)top1;
+    carry = rdlane((uint32_t)topv, 63u);  // at most ag < 2^32
+    return wave_min(cand);
+  }
+
+  // The lowest p >= lo with granules [p, p + s) all free, or kNone.  Node
+  // steps stop once they begin at or past below_end + s (only starts below
+  // below_end are wanted then).
   __device__ uint32_t find(uint32_t lo, uint32_t s, uint64_t below_end = 1ull << 40) const {
     const uint32_t lane = lane_id();
-    uint64_t carry = 0;  // free granules in a row ending just below the step
-    for (uint32_t w0 = lo >> 6; w0 < nw && 64ull * w0 < below_end + s; w0 += 64u) {
-      const uint32_t wi = w0 + lane;
-      const uint64_t below = wi == (lo >> 6) ? (1ull << (lo & 63u)) - 1ull : 0ull;
-      const uint64_t w = load(wi) & ~below;
-      const bool full = w == ~0ull;
-      const uint32_t low1 = full ? 64u : ctz64u(~w);   // free run at the bottom
-      const uint32_t top1 = full ? 64u : clz64u(~w);   // free run at the top
-      // run reaching the bottom of this word: from the nearest lower lane
-      // whose word is not all free, or from before the step
+    uint64_t carry = 0;
+    uint32_t K = word_step(lo >> 12, lo, s, carry);
+    if (K != kNone) return K;
+    for (uint32_t n1 = (lo >> 12) + 1u;
+         n1 < nn && (uint64_t)kNodeGranules * n1 < below_end + s;) {
+      const uint32_t ni = n1 + lane;
+      const uint64_t r = load_node(ni);
+      const uint32_t low1 = node_low(r), top1 = node_top(r);
+      const bool full = low1 == kNodeGranules;
       const uint64_t lt = ballot(!full) & ((1ull << lane) - 1ull);
       const uint32_t ps = lt ? 63u - clz64u(lt) : 0u;
       const uint32_t tp = shfl(top1, ps);
-      const uint64_t pre = lt ? (uint64_t)tp + 64ull * (lane - 1u - ps)
-                              : carry + 64ull * lane;
-      const uint64_t base = 64ull * wi;
-      // a run that reaches s in this word, having started below it
-      uint32_t cand = (pre < s && pre + low1 >= s) ? (uint32_t)(base - pre) : kNone;
-      // a run of s inside this word
-      if (s <= 64u) {
-        uint64_t y = w;
-        for (uint32_t k = 1; k < s;) {
-          const uint32_t d = k < s - k ? k : s - k;
-          y &= y >> d;
-          k += d;
-        }
-        const uint32_t in = y ? (uint32_t)base + ctz64u(y) : kNone;
-        cand = in < cand ? in : cand;
+      const uint64_t pre = lt ? (uint64_t)tp + (uint64_t)kNodeGranules * (lane - 1u - ps)
+                              : carry + (uint64_t)kNodeGranules * lane;
+      // the first node where a run reaches its s-th granule
+      const bool hit = (pre < s && pre + low1 >= s) || node_max(r) >= s;
+      const uint32_t d = wave_min(hit && ni < nn ? ni : kNone);
+      if (d != kNone) {
+        uint64_t c2 = rdlane((uint32_t)pre, d - n1);  // pre <= ag < 2^32
+        K = word_step(d, 0u, s, c2);
+        if (K != kNone) return K;
+        carry = c2;  // the summaries promised a run: not reached while they are exact
+        n1 = d + 1u;
+        continue;
       }
-      const uint32_t K = wave_min(cand);
-      if (K != kNone) return K;
-      const uint64_t topv = full ? pre + 64ull : (uint64_t)top1;
-      carry = rdlane((uint32_t)topv, 63u);  // at most ag < 2^32
+      const uint64_t topv = full ? pre + kNodeGranules : (uint64_t)top1;
+      carry = rdlane((uint32_t)topv, 63u);
+      n1 += 64u;
     }
     return kNone;
   }
 
-  // Granules [p, p + s) become free (set) or used (cleared); one word per lane.
+  // Granules [p, p + s) become free (set) or used (cleared), node by node:
+  // each lane one word of the node, then the node's summary.
   __device__ void mark(uint32_t p, uint32_t s, bool set) {
-    const uint32_t last = (p + s - 1u) >> 6;
-    for (uint32_t w0 = p >> 6; w0 <= last; w0 += 64u) {
-      const uint32_t wi = w0 + lane_id();
-      if (wi <= last) {
-        const uint64_t b0 = 64ull * wi;
-        const uint32_t lo = (uint32_t)((uint64_t)p > b0 ? (uint64_t)p - b0 : 0ull);
-        const uint64_t e = (uint64_t)p + s - b0;
-        const uint32_t hi = (uint32_t)(e < 64ull ? e : 64ull);
-        const uint64_t m = (hi == 64u ? ~0ull : (1ull << hi) - 1ull) & ~((1ull << lo) - 1ull);
-        const uint64_t v = bits[wi];
-        bits[wi] = set ? (v | m) : (v & ~m);
-      }
+    const uint32_t first = p >> 6, last = (p + s - 1u) >> 6;
+    for (uint32_t n = p >> 12; n <= (last >> 6); ++n) {
+      const uint32_t wi = 64u * n + lane_id();
+      const bool in = wi >= first && wi <= last;
+      const uint64_t b0 = 64ull * wi;
+      const uint32_t lo = (uint32_t)((uint64_t)p > b0 ? (uint64_t)p - b0 : 0ull);
+      const uint64_t e = (uint64_t)p + s - b0;
+      const uint32_t hi = (uint32_t)(e < 64ull ? e : 64ull);
+      const uint64_t m = in ? (hi == 64u ? ~0ull : (1ull << hi) - 1ull) & ~((1ull << (lo & 63u)) - 1ull)
+                            : 0ull;
+      const uint64_t v = load(wi);
+      const uint64_t nv = set ? (v | m) : (v & ~m);
+      if (in) bits[wi] = nv;
+      const uint64_t sum = node_summary(nv);
+      if (lane_id() == 0u) nodes[n] = sum;
     }
   }
 

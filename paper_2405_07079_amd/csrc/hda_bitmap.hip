@@ -18,10 +18,12 @@ namespace {
 constexpr uint32_t kWavesPerGroup = 4;
 constexpr int64_t kMaxWaves = 4096;
 
-// Workspace words of one wave's slot: the flags of max_granules, then the
-// live table.
+// Workspace words of one wave's slot: the flags of max_granules, their node
+// summaries (one per 64 words), then the live table.
+__host__ __device__ uint64_t flag_words(uint64_t max_granules) { return (max_granules + 63u) / 64u; }
+__host__ __device__ uint64_t node_words(uint64_t max_granules) { return (flag_words(max_granules) + 63u) / 64u; }
 uint64_t slot_words(uint64_t max_granules, int64_t cap_live) {
-  return (max_granules + 63u) / 64u + (uint64_t)cap_live;
+  return flag_words(max_granules) + node_words(max_granules) + (uint64_t)cap_live;
 }
 
 int64_t n_waves(int64_t heaps) { return heaps < kMaxWaves ? heaps : kMaxWaves; }
@@ -35,9 +37,10 @@ __global__ __launch_bounds__(64 * kWavesPerGroup) void bitmap_kernel(ReplayParam
   if (wave >= waves) return;
   uint64_t* slot = ws + (uint64_t)wave * words;
   uint64_t* bits = slot;
-  Ent* live = reinterpret_cast<Ent*>(slot + (max_granules + 63u) / 64u);
+  uint64_t* nodes = slot + flag_words(max_granules);
+  Ent* live = reinterpret_cast<Ent*>(nodes + node_words(max_granules));
   for (int64_t i = wave; i < p.n_heaps; i += waves)
-    bitmap_one_heap(p, bits, live, max_granules, p.order ? p.order[i] : i);
+    bitmap_one_heap(p, bits, nodes, live, max_granules, p.order ? p.order[i] : i);
 }
 
 bool desc_ok(const hda_batch_desc* d, uint64_t max_granules) {

@@ -230,16 +230,17 @@ __device__ void replay_any_heap(const ReplayParams& p, const Cold& c, int64_t he
 }
 
 // Bitmask-allocator replay of one heap (hda_bitmap.h) in a workspace slot
-// of max_granules flags and p.cap_live live entries; a heap of another
-// algorithm or a larger arena is rejected.
-__device__ __forceinline__ void bitmap_one_heap(const ReplayParams& p, uint64_t* bits, Ent* live,
+// of max_granules flags, their node summaries and p.cap_live live entries; a
+// heap of another algorithm or a larger arena is rejected.
+__device__ __forceinline__ void bitmap_one_heap(const ReplayParams& p, uint64_t* bits,
+                                                uint64_t* nodes, Ent* live,
                                                 uint64_t max_granules, int64_t heap) {
   HeapRegs h;
   if (!heap_params(p, heap, h) || h.algo != kBitmap || (uint64_t)h.ag > max_granules) {
     reject_heap(p, heap);
     return;
   }
-  BitHeap w(bits, live, h, p.cap_live);
+  BitHeap w(bits, nodes, live, h, p.cap_live);
   w.init();
   int32_t st = 0;
   run_requests<kBitmap>(p, w, p.req_off[heap], p.req_off[heap + 1], h.shift, h.arena, st);

@@ -58,8 +58,10 @@ def replay(batch, kf=64, kl=64, cf=4096, cl=4096, shape=2, overflowed=None):
     sl = np.zeros(H, np.int64)
     status = np.zeros(H, np.int32)
     syncs = np.zeros(H, np.uint64)
-    lib().emu_replay(H, P(arena), P(align), P(algo), P(off), P(req), P(res), P(state),
-                     P(so), P(sl), P(status), int(shape), kf, kl, cf, cl, P(syncs),
-                     None if overflowed is None else P(overflowed))
+    rc = lib().emu_replay(H, P(arena), P(align), P(algo), P(off), P(req), P(res), P(state),
+                          P(so), P(sl), P(status), int(shape), kf, kl, cf, cl, P(syncs),
+                          None if overflowed is None else P(overflowed))
+    # 1: a bitmask heap's node summaries disagree with its flags
+    assert rc == 0, "bitmask node summaries are not exact" if rc == 1 else rc
     states = [state[so[h]:so[h] + sl[h]].copy() for h in range(H)]
     return res, states, status, syncs

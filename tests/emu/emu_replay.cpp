@@ -27,7 +27,8 @@ struct LaneJob {
   int64_t heap;
   int shape;
   int done;
-  uint64_t* bits;        // bitmask allocator: flags and live table
+  uint64_t* bits;        // bitmask allocator: flags, node summaries, live table
+  uint64_t* nodes;
   Ent* live;
   uint64_t max_granules;
 };
@@ -52,7 +53,8 @@ void lane_main() {
     case 3: lean_any<1>(*g_job.p, *g_job.lds, *g_job.c, g_job.heap); break;
     case 4: lean_any<4>(*g_job.p, *g_job.lds, *g_job.c, g_job.heap); break;
     default:
-      bitmap_one_heap(*g_job.p, g_job.bits, g_job.live, g_job.max_granules, g_job.heap);
+      bitmap_one_heap(*g_job.p, g_job.bits, g_job.nodes, g_job.live, g_job.max_granules,
+                      g_job.heap);
       break;
   }
   // a finished lane keeps handing over until every lane has finished
@@ -68,6 +70,28 @@ void lane_main() {
 }
 
 const int kShapeRF[] = {0, 1, 4, 0, 0, 0}, kShapeRL[] = {0, 2, 8, 0, 0, 0};
+
+// The bitmask allocator's node summaries recomputed granule by granule from
+// the flags: bottom run | top run << 16 | longest run << 32 per 4,096
+// granules.  True if every stored summary matches.
+bool summaries_exact(const uint64_t* bits, const uint64_t* nodes, uint64_t ag) {
+  const uint64_t nw = (ag + 63u) / 64u, nn = (nw + 63u) / 64u;
+  for (uint64_t n = 0; n < nn; ++n) {
+    auto is_free = [&](uint64_t g) {  // g inside the node
+      const uint64_t x = 4096u * n + g;
+      return x < ag && ((bits[x / 64u] >> (x % 64u)) & 1u) != 0;
+    };
+    uint64_t bottom = 0, top = 0, best = 0, run = 0;
+    while (bottom < 4096u && is_free(bottom)) ++bottom;
+    while (top < 4096u && is_free(4095u - top)) ++top;
+    for (uint64_t g = 0; g < 4096u; ++g) {
+      run = is_free(g) ? run + 1u : 0u;
+      best = run > best ? run : best;
+    }
+    if (nodes[n] != (bottom | (top << 16) | (best << 32))) return false;
+  }
+  return true;
+}
 
 // Run one heap as a wave of 64 fibers.
 void run_wave(EmuWave& w, std::vector<std::vector<uint8_t>>& stacks) {
@@ -147,13 +171,17 @@ extern "C" int emu_replay(int64_t H, const int64_t* arena, const int64_t* align,
       n_sync = w.syncs;
       if (overflowed) overflowed[h] = migrated != before;
     } else if (shape == 5) {
-      // poisoned flags past the heap's words and a poisoned live table
+      // poisoned flags and summaries past the heap's words and a poisoned
+      // live table
       const uint64_t ag = (align[h] > 0 && arena[h] > 0) ? uint64_t(arena[h] / align[h]) : 1u;
-      std::vector<uint64_t> bits((ag + 63u) / 64u + 1u, 0xA5A5A5A5A5A5A5A5ull);
+      const uint64_t nw = (ag + 63u) / 64u;
+      std::vector<uint64_t> bits(nw + 1u, 0xA5A5A5A5A5A5A5A5ull);
+      std::vector<uint64_t> nodes((nw + 63u) / 64u + 1u, 0xA5A5A5A5A5A5A5A5ull);
       std::vector<Ent> live(size_t(cap_live) + 1u, 0xA5A5A5A5A5A5A5A5ull);
-      g_job = LaneJob{&p, &c, nullptr, h, shape, 0, bits.data(), live.data(), ag};
+      g_job = LaneJob{&p, &c, nullptr, h, shape, 0, bits.data(), nodes.data(), live.data(), ag};
       run_wave(w, stacks);
       n_sync = w.syncs;
+      if (status[h] == 0 && !summaries_exact(bits.data(), nodes.data(), ag)) return 1;
     } else {
       g_job = LaneJob{&p, &c, nullptr, h, shape, 0};
       run_wave(w, stacks);

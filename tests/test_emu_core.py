@@ -240,10 +240,11 @@ def test_bitmap_random_small_heaps():
     check(b, res, states, status)
 
 
-@pytest.mark.parametrize("granules,hi", ((5000, 200), (9000, 9000), (70_000, 3000)))
+@pytest.mark.parametrize("granules,hi", ((5000, 200), (9000, 9000), (70_000, 3000),
+                                         (600_000, 60_000), (300_000, 4)))
 def test_bitmap_runs_across_words_and_steps(granules, hi):
-    """Arenas of several 4,096-granule scan steps and runs longer than a word
-    or a step."""
+    """Arenas of several 4,096-granule nodes, runs longer than a word or a
+    node, and more than 64 nodes (node summaries read in several steps)."""
     b = W.random_tiny(granules, 600, granules, align=16, algo=5, max_granules=hi,
                       p_partial=0.2)
     res, states, status, _ = emu.replay(b, cf=4096, cl=4096, shape=5)

@@ -58,6 +58,18 @@ def test_16MiB_heaps_reduced():
     check(b, *run(b))
 
 
+def test_more_than_64_nodes():
+    """Arenas past 262,144 granules: the node summaries take several steps
+    of 64, and runs span nodes."""
+    parts = [W.random_tiny(40 + k, 3000, g, align=16, algo=BM, max_granules=hi,
+                           p_partial=0.1)
+             for k, (g, hi) in enumerate(((300_000, 4), (600_000, 60_000),
+                                          (1_500_000, 200_000), (262_145, 5000)))]
+    b = W.concat(parts)
+    say(f"case: {b.heaps} bitmask heaps of 262,145-1,500,000 granules, {b.requests} requests")
+    check(b, *run(b))
+
+
 def test_rejections_and_capacity():
     good = W.random_tiny(1, 200, 500, align=16, algo=BM)
     other = W.random_tiny(2, 200, 500, align=16, algo=0)     # not a bitmask heap
