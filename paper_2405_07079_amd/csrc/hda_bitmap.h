@@ -115,13 +115,15 @@ struct BitHeap {
   int64_t arena;
   uint32_t shift, ag, nw, nn;
   uint32_t L, rover, capL;
+  uint32_t cn;  // node whose words the last word step or mark left in cw, or kNone
+  uint64_t cw;  // that node's word of this lane (no mask applied)
 
   __device__ __forceinline__ BitHeap(uint64_t* b, uint64_t* nd, Ent* lv, const HeapRegs& h,
                                      uint32_t cap_live)
       : bits((HDA_GLOBAL uint64_t*)b), nodes((HDA_GLOBAL uint64_t*)nd),
         live((HDA_GLOBAL Ent*)lv), arena(h.arena), shift(h.shift), ag(h.ag),
         nw((h.ag + 63u) >> 6), nn((((h.ag + 63u) >> 6) + 63u) >> 6), L(0), rover(0),
-        capL(cap_live) {}
+        capL(cap_live), cn(kNone), cw(0) {}
 
   // word wi, or 0 past the end (the load is clamped, not branched around)
   __device__ __forceinline__ uint64_t load(uint32_t wi) const {
@@ -149,6 +151,7 @@ struct BitHeap {
     }
     L = 0;
     rover = 0;
+    cn = kNone;
   }
 
   // One step over node n's 64 words: the lowest p >= lo whose s-th granule
@@ -156,12 +159,14 @@ struct BitHeap {
   // just below the node (granules below lo count as used), or kNone; carry
   // becomes the free run ending at the node's top.
   __device__ __forceinline__ uint32_t word_step(uint32_t n, uint32_t lo, uint32_t s,
-                                                uint64_t& carry) const {
+                                                uint64_t& carry) {
     const uint32_t lane = lane_id();
     const uint32_t wi = 64u * n + lane;
     const uint32_t lw = lo >> 6;
     const uint64_t below = wi < lw ? ~0ull : wi == lw ? (1ull << (lo & 63u)) - 1ull : 0ull;
-    const uint64_t w = load(wi) & ~below;
+    cw = load(wi);
+    cn = n;
+    const uint64_t w = cw & ~below;
     const bool full = w == ~0ull;
     const uint32_t low1 = full ? 64u : ctz64u(~w);   // free run at the bottom
     const uint32_t top1 = full ? 64u : clz64u(~w);   // free run at the top
@@ -190,16 +195,17 @@ struct BitHeap {
 
   // The lowest p >= lo with granules [p, p + s) all free, or kNone.  Node
   // steps stop once they begin at or past below_end + s (only starts below
-  // below_end are wanted then).
-  __device__ uint32_t find(uint32_t lo, uint32_t s, uint64_t below_end = 1ull << 40) const {
+  // below_end are wanted then).  The first node step's summaries are read
+  // together with the first word step's words.
+  __device__ uint32_t find(uint32_t lo, uint32_t s, uint64_t below_end = 1ull << 40) {
     const uint32_t lane = lane_id();
+    uint32_t n1 = (lo >> 12) + 1u;
+    uint64_t r = load_node(n1 + lane);
     uint64_t carry = 0;
     uint32_t K = word_step(lo >> 12, lo, s, carry);
     if (K != kNone) return K;
-    for (uint32_t n1 = (lo >> 12) + 1u;
-         n1 < nn && (uint64_t)kNodeGranules * n1 < below_end + s;) {
+    while (n1 < nn && (uint64_t)kNodeGranules * n1 < below_end + s) {
       const uint32_t ni = n1 + lane;
-      const uint64_t r = load_node(ni);
       const uint32_t low1 = node_low(r), top1 = node_top(r);
       const bool full = low1 == kNodeGranules;
       const uint64_t lt = ballot(!full) & ((1ull << lane) - 1ull);
@@ -216,17 +222,20 @@ struct BitHeap {
         if (K != kNone) return K;
         carry = c2;  // the summaries promised a run: not reached while they are exact
         n1 = d + 1u;
+        r = load_node(n1 + lane);
         continue;
       }
       const uint64_t topv = full ? pre + kNodeGranules : (uint64_t)top1;
       carry = rdlane((uint32_t)topv, 63u);
       n1 += 64u;
+      r = load_node(n1 + lane);
     }
     return kNone;
   }
 
   // Granules [p, p + s) become free (set) or used (cleared), node by node:
-  // each lane one word of the node, then the node's summary.
+  // each lane one word of the node (the words a search just read are reused),
+  // then the node's summary.
   __device__ void mark(uint32_t p, uint32_t s, bool set) {
     const uint32_t first = p >> 6, last = (p + s - 1u) >> 6;
     for (uint32_t n = p >> 12; n <= (last >> 6); ++n) {
@@ -238,9 +247,15 @@ struct BitHeap {
       const uint32_t hi = (uint32_t)(e < 64ull ? e : 64ull);
       const uint64_t m = in ? (hi == 64u ? ~0ull : (1ull << hi) - 1ull) & ~((1ull << (lo & 63u)) - 1ull)
                             : 0ull;
-      const uint64_t v = load(wi);
+      uint64_t v;
+      if (n == cn)
+        v = cw;
+      else
+        v = load(wi);
       const uint64_t nv = set ? (v | m) : (v & ~m);
       if (in) bits[wi] = nv;
+      cn = n;
+      cw = nv;
       const uint64_t sum = node_summary(nv);
       if (lane_id() == 0u) nodes[n] = sum;
     }
