@@ -122,7 +122,8 @@ struct BitHeap {
                                      uint32_t cap_live)
       : bits((HDA_GLOBAL uint64_t*)b), nodes((HDA_GLOBAL uint64_t*)nd),
         live((HDA_GLOBAL Ent*)lv), arena(h.arena), shift(h.shift), ag(h.ag),
-        nw((h.ag + 63u) >> 6), nn((((h.ag + 63u) >> 6) + 63u) >> 6), L(0), rover(0),
+        nw((uint32_t)(((uint64_t)h.ag + 63u) >> 6)),  // ag may be 2^32 - 1
+        nn((uint32_t)(((uint64_t)h.ag + 4095u) >> 12)), L(0), rover(0),
         capL(cap_live), cn(kNone), cw(0) {}
 
   // word wi, or 0 past the end (the load is clamped, not branched around)

@@ -70,6 +70,19 @@ def test_more_than_64_nodes():
     check(b, *run(b))
 
 
+def test_max_arena():
+    """The largest arena, 2^32 - 1 granules of 64 B (256 GiB of flags' worth,
+    512 MiB of flags): ragged last word and node, blocks that end at the
+    arena's last granule, whole-arena requests, wrapping searches (the two
+    hand-written traces the table kernels are tested on at this size)."""
+    mb = W.max_arena_batch()
+    per_trace = mb.heaps // 2
+    b = mb.subset([0, per_trace]).with_algo(BM)
+    assert int(b.arena[0] // b.align[0]) == (1 << 32) - 1
+    say(f"case: 2 bitmask heaps of 2^32 - 1 granules, {b.requests} requests")
+    check(b, *run(b, meta_live=64))
+
+
 def test_rejections_and_capacity():
     good = W.random_tiny(1, 200, 500, align=16, algo=BM)
     other = W.random_tiny(2, 200, 500, align=16, algo=0)     # not a bitmask heap
