@@ -84,7 +84,11 @@ __device__ __forceinline__ uint32_t node_low(uint64_t r) { return (uint32_t)r & 
 __device__ __forceinline__ uint32_t node_top(uint64_t r) { return (uint32_t)(r >> 16) & 0xffffu; }
 __device__ __forceinline__ uint32_t node_max(uint64_t r) { return (uint32_t)(r >> 32); }
 
-// Summary of the node whose word `lane` is w (all lanes).
+// Summary of the node whose word `lane` is w (all lanes).  The longest run
+// is the longest of the runs that reach a word boundary (they end at the
+// bottom of the next word that is not all free, or at the node's top) and
+// the runs inside single words; a word's inner runs are measured only when
+// its free granules outnumber the longest boundary run.
 __device__ __forceinline__ uint64_t node_summary(uint64_t w) {
   const uint32_t lane = lane_id();
   const bool full = w == ~0ull;
@@ -97,10 +101,13 @@ __device__ __forceinline__ uint64_t node_summary(uint64_t w) {
   // free run ending just below this word, inside the node
   const uint32_t pre = lt ? tp + 64u * (lane - 1u - ps) : 64u * lane;
   const uint32_t topv = full ? pre + 64u : top1;  // free run ending at this word's top
-  uint32_t m = longest_run(w);
-  m = (!full && pre + low1 > m) ? pre + low1 : m;
+  uint32_t m = full ? 0u : pre + low1;
   m = (lane == 63u && topv > m) ? topv : m;
-  const uint32_t mx = rdlane(wave_scan_max(m), 63u);
+  uint32_t mx = rdlane(wave_scan_max(m), 63u);
+  if (ballot(!full && popc64(w) > mx)) {  // wave-uniform
+    const uint32_t inner = rdlane(wave_scan_max(longest_run(w)), 63u);
+    mx = inner > mx ? inner : mx;
+  }
   const uint32_t fl = nf ? ctz64u(nf) : 0u;
   const uint32_t lw = rdlane(low1, fl);
   const uint32_t bottom = nf ? 64u * fl + lw : kNodeGranules;
