@@ -150,11 +150,14 @@ typedef struct hda_batch_desc {
 
 /* Bitmask-allocator replay (Sec. III-B): every heap of `d` must be
  * HDA_BITMAP with arena / align <= max_granules (< 2^32); other heaps get
- * HDA_E_INVAL as status and as every result.  One wavefront per heap scans
- * 64 words of flags (4,096 granules) per step.  Requests, results, states
- * and statuses as for hda_replay (partial frees included; the live table
- * holds meta_live entries, HDA_E_NOMETA past it; meta_free is not used).
- * The workspace holds each wave's flags and live table:
+ * HDA_E_INVAL as status and as every result.  One wavefront per heap keeps
+ * one flag per granule and a summary per 4,096 granules (free runs at the
+ * bottom, at the top, longest), and searches 64 words of flags or 64
+ * summaries per step.  Requests, results, states and statuses as for
+ * hda_replay (partial frees included; the live table holds meta_live
+ * entries, HDA_E_NOMETA past it; meta_free is not used).  The workspace
+ * holds each wave's flags, summaries and live table, about
+ * max_granules / 8 + 8 * meta_live bytes per wave for up to 4,096 waves:
  * hda_bitmap_workspace(d, max_granules) bytes (0 on invalid arguments).
  * Asynchronous on `stream`; HDA_E_RANGE if the workspace is too small. */
 size_t hda_bitmap_workspace(const hda_batch_desc *d, uint64_t max_granules);
