@@ -123,6 +123,27 @@ def issue_roofline(per_algo_ops):
     return out
 
 
+def bitmap_issue(ops):
+    """The bitmask-allocator kernel's issue at `ops` requests/s, from the
+    per-request counts in its committed instruction-mix summary while the
+    kernel sources match; else None."""
+    import re
+    path = os.path.join(ROOT, "profiles", "bitmap_c2_instruction_mix.txt")
+    try:
+        with open(path) as f:
+            text = f.read()
+    except OSError:
+        return None
+    m = re.search(r"^\s+VALU ([0-9.]+)\s+SALU ([0-9.]+)", text, re.M)
+    if kernel_source_hash() not in text or not m:
+        return None
+    valu, salu = float(m.group(1)), float(m.group(2))
+    return {"bound": "issue", "unit": "G wave-instructions/s",
+            "peak_valu": VALU_ISSUE_PEAK / 1e9, "peak_salu": SALU_ISSUE_PEAK / 1e9,
+            "valu_per_request": valu, "salu_per_request": salu,
+            "valu_frac": valu * ops / VALU_ISSUE_PEAK, "salu_frac": salu * ops / SALU_ISSUE_PEAK}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -403,6 +424,7 @@ def main():
                               "per granule, 32 KiB per heap; next-fit scan from the rover)",
                   "value": batch.requests / (float(np.median(bms)) / 1e3), "unit": "ops/s",
                   "launch_ms": float(np.median(bms))}
+        bitmap["issue"] = bitmap_issue(bitmap["value"])
         del bdb
         log(f"[bench] bitmap: {bitmap['value'] / 1e9:.3f} G ops/s")
 
