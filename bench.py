@@ -56,7 +56,7 @@ def recorded_traffic(algo_names):
     WRITE_SIZE, calibrated on a copy kernel), averaged over the timed
     launches; None when the summary is missing or was taken on other kernel
     sources."""
-    path = os.path.join(ROOT, "profiles", "replay_c2_hbm_traffic.txt")
+    path = os.path.join(ROOT, "profiles", "replay_4096x16MiB_hbm_traffic.txt")
     try:
         with open(path) as f:
             line = [x for x in f if x.startswith("machine-readable: ")][-1]
@@ -75,7 +75,7 @@ def recorded_mix():
     """Per-request counts from the committed instruction-mix summary, while
     the kernel sources match: {algorithm: {"valu", "salu", "lds", "branch",
     "lds_conflict_cycles"}}; else None."""
-    path = os.path.join(ROOT, "profiles", "replay_c2_instruction_mix.txt")
+    path = os.path.join(ROOT, "profiles", "replay_4096x16MiB_instruction_mix.txt")
     try:
         with open(path) as f:
             text = f.read()
@@ -128,7 +128,7 @@ def bitmap_issue(ops):
     per-request counts in its committed instruction-mix summary while the
     kernel sources match; else None."""
     import re
-    path = os.path.join(ROOT, "profiles", "bitmap_c2_instruction_mix.txt")
+    path = os.path.join(ROOT, "profiles", "bitmap_4096x16MiB_instruction_mix.txt")
     try:
         with open(path) as f:
             text = f.read()

@@ -26,7 +26,7 @@ def profile_matches(name):
 
 def test_bitmap_issue_from_profile():
     r = bench.bitmap_issue(2e9)
-    if not profile_matches("bitmap_c2_instruction_mix.txt"):
+    if not profile_matches("bitmap_4096x16MiB_instruction_mix.txt"):
         assert r is None          # figures of other sources are not reported
         return
     assert r["valu_per_request"] > 0 and r["salu_per_request"] > 0
@@ -36,7 +36,7 @@ def test_bitmap_issue_from_profile():
 
 def test_replay_issue_from_profile():
     r = bench.issue_roofline({"best_fit": 5e9, "seg_fit": 4e9})
-    if not profile_matches("replay_c2_instruction_mix.txt"):
+    if not profile_matches("replay_4096x16MiB_instruction_mix.txt"):
         assert r is None
         return
     for name, ops in (("best_fit", 5e9), ("seg_fit", 4e9)):
