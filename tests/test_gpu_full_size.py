@@ -44,13 +44,13 @@ def check_heaps(batch, res, db, status, heaps):
 
 
 @pytest.fixture(scope="module")
-def c2():
+def batch_4096():
     return W.uniform_batch()
 
 
 @pytest.mark.parametrize("algo", (W.BEST_FIT, W.SEG_FIT, W.TLSF))
-def test_4096_heaps_full_size_sampled(c2, algo):
-    b = c2.with_algo(algo)
+def test_4096_heaps_full_size_sampled(batch_4096, algo):
+    b = batch_4096.with_algo(algo)
     say(f"case: 4096 x 16 MiB heaps, 100k requests each, algo {algo}")
     db = hda.upload(b)
     hda.hda_replay(db)
@@ -66,10 +66,10 @@ def test_4096_heaps_full_size_sampled(c2, algo):
     check_heaps(b, res, db, status, heaps)
 
 
-def test_4096_heaps_bitmap_full_size_sampled(c2):
+def test_4096_heaps_bitmap_full_size_sampled(batch_4096):
     """The benchmark's bitmask-allocator leg: the same batch, one flag per
     granule; 24 sampled heaps element by element."""
-    b = c2.with_algo(W.BITMAP)
+    b = batch_4096.with_algo(W.BITMAP)
     say("case: 4096 x 16 MiB heaps, 100k requests each, bitmask allocator")
     db = hda.upload(b)
     hda.hda_bitmap_replay(db, hda.max_granules(b))
