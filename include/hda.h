@@ -65,6 +65,27 @@ enum {
 };
 
 /* ------------------------------------------------------------------------ */
+/* Device memory the library keeps for itself.                              */
+/* ------------------------------------------------------------------------ */
+
+/* The library's own device buffers -- call-by-call heap metadata and result
+ * buffers, the service's heap pool, the autotuner's trial batch -- are
+ * obtained from `alloc` and returned to `release`, each called with `ctx`
+ * (for instance the caller's caching allocator); with none installed (both
+ * NULL, the default) hipMalloc / hipFree are used.  `alloc` returns device
+ * memory of at least `bytes` bytes, 256-byte aligned, or NULL (the library
+ * call then fails with HDA_E_DEVICE); the library never touches a buffer
+ * after releasing it and releases it only once its own work on it has
+ * completed.  Callbacks run on the thread that made the library call.
+ * HDA_E_INVAL if exactly one of the two is NULL; HDA_E_BUSY while buffers
+ * from the allocator installed before are still held (release them first:
+ * destroy heaps, stop the service).  Batch buffers and workspaces of the
+ * replay calls are always the caller's. */
+typedef void *(*hda_dev_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*hda_dev_free_fn)(void *ptr, void *ctx);
+int hda_set_device_allocator(hda_dev_alloc_fn alloc, hda_dev_free_fn release, void *ctx);
+
+/* ------------------------------------------------------------------------ */
 /* Batched replay (many independent heaps, one persistent launch).          */
 /* ------------------------------------------------------------------------ */
 
@@ -219,8 +240,10 @@ int hda_graph_destroy(hda_graph *g);
 typedef struct hda_heap hda_heap; /* opaque, library-owned */
 
 /* Create a heap over a virtual arena of arena_bytes (Alg. 6: one free block
- * [0, arena_bytes)).  Metadata lives in device memory owned by the library:
- * meta_cap bounds both the free-table and the live-table entries (0 = 4096).
+ * [0, arena_bytes)).  Metadata lives in device memory the library obtains
+ * from the installed device allocator (hda_set_device_allocator): meta_cap
+ * bounds both the free-table and the live-table entries (0 = 4096).  Calls
+ * on heaps of one device run on one library stream of that device.
  * HDA_E_INVAL: align not a power of two, arena_bytes == 0 or not a multiple
  * of align, arena_bytes / align >= 2^32, unknown algo, out == NULL.
  * HDA_E_NOMETA: the metadata budget (hda_set_meta_budget) is exhausted.
@@ -254,6 +277,23 @@ int hda_free_partial(hda_heap *h, int64_t offset);
  * `cap` words; *len receives the words needed.  HDA_E_RANGE if cap < *len.
  * Synchronous. */
 int hda_heap_state(const hda_heap *h, int64_t *buf, size_t cap, size_t *len);
+
+/* Resume a heap from a canonical state (the format above, as written by
+ * hda_heap_state or by a replay's state dump) of a heap with the same arena,
+ * alignment and algorithm: the free blocks, the live blocks in live-table
+ * order, the next-fit rover and the class lists in head-to-tail order all
+ * become this heap's (Alg. 6 initialises a heap from one block; this
+ * initialises it from any reachable state).  `buf` is a host buffer of `len`
+ * words.  HDA_E_INVAL, heap unchanged, when the state is malformed or not a
+ * state of this heap: words missing or left over, free blocks not in
+ * ascending address order, blocks that are unaligned, empty, overlapping or
+ * do not tile [0, arena), two adjacent free blocks, a rover outside
+ * [0, arena] or unaligned (next fit) or not -1 (the others), a bitmap that
+ * does not match the lists, a free block in no list, in the wrong list or in
+ * two (segregated fit, TLSF), lists or a bitmap on the other algorithms.
+ * HDA_E_NOMETA, heap unchanged, when the blocks exceed the heap's metadata
+ * capacity.  Synchronous. */
+int hda_heap_load(hda_heap *h, const int64_t *buf, size_t len);
 
 /* Metadata budget (bytes of device memory all live heaps may hold);
  * 0 = unlimited (the default).  Returns the bytes currently held. */

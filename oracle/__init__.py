@@ -128,12 +128,14 @@ def state_capacity(algo: int, n_requests: int, cap_blocks: int | None = None):
 
 
 def replay_batch(batch, threads: int = 1, want_state: bool = True,
-                 want_stats: bool = False):
+                 want_stats: bool = False, state_blocks: int | None = None):
     """Replay every heap of a ``workloads.Batch``.
 
     Returns ``(res, states, stats)``: results aligned with ``batch.req``, a list
     of per-heap state arrays (or None) and per-heap (examined, touched) counts
-    (or None).
+    (or None).  ``state_blocks`` bounds the blocks a heap's state slot is sized
+    for (default: one more than its requests); a heap whose state needs more
+    words gets an empty array, which no real state equals.
     """
     H = batch.heaps
     arena = np.ascontiguousarray(batch.arena, np.int64)
@@ -145,8 +147,10 @@ def replay_batch(batch, threads: int = 1, want_state: bool = True,
     state = state_off = state_len = None
     if want_state:
         lens = np.diff(off)
-        caps = np.array([state_capacity(int(a), int(n)) for a, n in zip(algo, lens)],
-                        np.int64)
+        caps = np.array([state_capacity(int(a), int(n),
+                                        None if state_blocks is None
+                                        else min(int(n) + 1, int(state_blocks)))
+                         for a, n in zip(algo, lens)], np.int64)
         state_off = np.zeros(H + 1, np.int64)
         np.cumsum(caps, out=state_off[1:])
         state = np.empty(int(state_off[-1]), np.int64)
@@ -159,7 +163,9 @@ def replay_batch(batch, threads: int = 1, want_state: bool = True,
         raise ValueError(f"oracle rejected the batch (code {rc})")
     states = None
     if want_state:
-        states = [state[state_off[i]:state_off[i] + state_len[i]].copy() for i in range(H)]
+        states = [state[state_off[i]:state_off[i] + state_len[i]].copy()
+                  if state_len[i] <= state_off[i + 1] - state_off[i] else np.zeros(0, np.int64)
+                  for i in range(H)]
     return res, states, (stats.reshape(H, 2) if want_stats else None)
 
 

@@ -4,16 +4,19 @@
 // of the same core as the batched replay, and stores them back.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdint>
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <vector>
 
 #include "hda.h"
 #include "hda_wave.h"
 #include "hda_core.h"
 #include "hda_heap_dev.h"
+#include "hda_mem.h"
 
 using namespace hda;
 
@@ -54,14 +57,69 @@ __global__ void heap_call(HeapHdr* hd, int op, int64_t arg, int64_t* out, int64_
 std::atomic<int64_t> g_budget{0};  // 0 = unlimited
 std::atomic<int64_t> g_held{0};
 
+// The installed device allocator (none: hipMalloc / hipFree) and the number
+// of buffers obtained from it that are still held.
+struct Allocator {
+  std::mutex mu;
+  hda_dev_alloc_fn alloc = nullptr;
+  hda_dev_free_fn release = nullptr;
+  void* ctx = nullptr;
+  int64_t held = 0;
+};
+Allocator& allocator() {
+  static Allocator a;
+  return a;
+}
+
 }  // namespace
+
+namespace hda {
+
+void* dev_alloc(size_t bytes) {
+  Allocator& a = allocator();
+  std::lock_guard<std::mutex> g(a.mu);
+  void* p = nullptr;
+  if (a.alloc) {
+    p = a.alloc(bytes, a.ctx);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) ++a.held;
+  return p;
+}
+
+void dev_free(void* p) {
+  if (!p) return;
+  Allocator& a = allocator();
+  std::lock_guard<std::mutex> g(a.mu);
+  if (a.release) a.release(p, a.ctx);
+  else (void)hipFree(p);
+  --a.held;
+}
+
+hipStream_t lib_stream() {
+  static std::mutex mu;
+  static std::vector<hipStream_t> streams;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return nullptr;
+  std::lock_guard<std::mutex> g(mu);
+  if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+  if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+    streams[dev] = nullptr;
+  return streams[dev];
+}
+
+}  // namespace hda
 
 struct hda_heap {
   HeapHdr* dev = nullptr;      // header + tables (device)
   int64_t* io = nullptr;       // device result / dump buffer
   size_t io_words = 0;
   size_t bytes = 0;            // metadata bytes charged to the budget
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;  // the library's stream of the heap's device
+  int algo = 0;
+  uint64_t arena = 0, align = 0;
+  uint32_t cap = 0;            // table capacities (entries)
   std::mutex mu;
 };
 
@@ -72,10 +130,14 @@ int call(hda_heap* h, int op, int64_t arg, int64_t* result, int64_t* dump, size_
   std::lock_guard<std::mutex> g(h->mu);
   const size_t need_io = (op == kOpDump) ? cap + 1 : 1;
   if (need_io > h->io_words) {
-    if (h->io) (void)hipFree(h->io);
+    if (h->io) {
+      (void)hipStreamSynchronize(h->stream);
+      dev_free(h->io);
+    }
     h->io = nullptr;
     h->io_words = 0;
-    if (hipMalloc(&h->io, need_io * 8) != hipSuccess) return HDA_E_DEVICE;
+    h->io = static_cast<int64_t*>(dev_alloc(need_io * 8));
+    if (!h->io) return HDA_E_DEVICE;
     h->io_words = need_io;
   }
   hipLaunchKernelGGL(heap_call, dim3(1), dim3(64), 0, h->stream, h->dev, op, arg, h->io,
@@ -88,11 +150,143 @@ int call(hda_heap* h, int op, int64_t arg, int64_t* result, int64_t* dump, size_
   if (op == kOpDump) {
     *len = (size_t)r;
     if ((size_t)r > cap) return HDA_E_RANGE;
-    if (r > 0 && hipMemcpy(dump, h->io + 1, (size_t)r * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    if (r > 0 && (hipMemcpyAsync(dump, h->io + 1, (size_t)r * 8, hipMemcpyDeviceToHost,
+                                 h->stream) != hipSuccess ||
+                  hipStreamSynchronize(h->stream) != hipSuccess))
       return HDA_E_DEVICE;
     return HDA_OK;
   }
   *result = r;
+  return HDA_OK;
+}
+
+}  // namespace
+
+
+namespace {
+
+int floor_log2_u64(uint64_t x) { return 63 - __builtin_clzll(x); }
+
+// TLSF list of a block of b bytes (fl * 32 + sl, as in the state format).
+uint32_t tlsf_list(uint64_t b) {
+  const int fl = floor_log2_u64(b);
+  const uint64_t sl = fl >= (int)kSli ? (b >> (fl - (int)kSli)) - kNsl : (b << ((int)kSli - fl)) - kNsl;
+  return (uint32_t)fl * kNsl + (uint32_t)sl;
+}
+
+// Check a canonical state (format in hda.h) for heap h and lay it out as the
+// device image of that heap: header, free table with push stamps, live
+// table.  The class lists' head-to-tail order becomes descending stamps
+// within each class, which is how the device core orders a list.  Returns
+// HDA_OK, HDA_E_INVAL (malformed, or not a state of this heap's arena,
+// alignment and algorithm) or HDA_E_NOMETA (more blocks than the tables
+// hold).
+int build_image(const hda_heap* h, const int64_t* buf, size_t len, std::vector<uint8_t>& img) {
+  const int64_t A = (int64_t)h->arena, g = (int64_t)h->align;
+  const int algo = h->algo;
+  const uint32_t shift = (uint32_t)__builtin_ctzll(h->align);
+  size_t p = 0;
+  auto word = [&](int64_t& v) {
+    if (p >= len) return false;
+    v = buf[p++];
+    return true;
+  };
+  struct Blk { int64_t a, s; bool free; };
+  std::vector<Blk> all;
+  int64_t nf = 0, nl = 0;
+  if (!word(nf) || nf < 0 || (uint64_t)nf > (len - p) / 2) return HDA_E_INVAL;
+  std::vector<Blk> fr((size_t)nf);
+  for (int64_t i = 0; i < nf; ++i) {
+    word(fr[i].a);
+    word(fr[i].s);
+    fr[i].free = true;
+    if (i > 0 && fr[i].a <= fr[i - 1].a) return HDA_E_INVAL;  // address order
+  }
+  if (!word(nl) || nl < 0 || (uint64_t)nl > (len - p) / 2) return HDA_E_INVAL;
+  std::vector<Blk> lv((size_t)nl);
+  for (int64_t i = 0; i < nl; ++i) {
+    word(lv[i].a);
+    word(lv[i].s);
+    lv[i].free = false;
+  }
+  int64_t rover = 0, bitmap = 0;
+  if (!word(rover) || !word(bitmap)) return HDA_E_INVAL;
+  // tiling of [0, A): aligned, positive, contiguous, no two free blocks adjacent
+  all = fr;
+  all.insert(all.end(), lv.begin(), lv.end());
+  std::sort(all.begin(), all.end(), [](const Blk& x, const Blk& y) { return x.a < y.a; });
+  int64_t pos = 0;
+  for (size_t i = 0; i < all.size(); ++i) {
+    const Blk& b = all[i];
+    if (b.a != pos || b.s <= 0 || b.s % g || b.s > A - pos) return HDA_E_INVAL;
+    if (i > 0 && b.free && all[i - 1].free) return HDA_E_INVAL;
+    pos += b.s;
+  }
+  if (pos != A) return HDA_E_INVAL;
+  if (algo == HDA_NEXT_FIT) {
+    if (rover < 0 || rover > A || rover % g) return HDA_E_INVAL;
+  } else if (rover != -1) {
+    return HDA_E_INVAL;
+  }
+  // class lists (segregated fit: 64 classes of floor(log2 bytes); TLSF: 2,048)
+  const bool seg = algo == HDA_SEG_FIT || algo == HDA_TLSF;
+  const uint32_t n_lists = algo == HDA_SEG_FIT ? 64u : algo == HDA_TLSF ? kTlsfClasses : 0u;
+  std::vector<uint32_t> stamp((size_t)nf, 0u);
+  uint64_t want_bitmap = 0;
+  uint32_t clock = 1;
+  for (uint32_t c = 0; c < n_lists; ++c) {
+    int64_t n = 0;
+    if (!word(n) || n < 0 || (uint64_t)n > len - p) return HDA_E_INVAL;
+    for (int64_t k = 0; k < n; ++k) {
+      int64_t a = 0;
+      word(a);
+      const auto it = std::lower_bound(fr.begin(), fr.end(), a,
+                                       [](const Blk& b, int64_t x) { return b.a < x; });
+      if (it == fr.end() || it->a != a) return HDA_E_INVAL;  // not a free block
+      const size_t i = (size_t)(it - fr.begin());
+      const uint64_t b = (uint64_t)it->s;
+      const uint32_t cls = algo == HDA_SEG_FIT ? (uint32_t)floor_log2_u64(b) : tlsf_list(b);
+      if (cls != c || stamp[i] != 0u) return HDA_E_INVAL;  // wrong list or listed twice
+      stamp[i] = clock + (uint32_t)(n - 1 - k);            // head: the newest push
+    }
+    clock += (uint32_t)n;
+    if (n > 0) want_bitmap |= 1ull << (algo == HDA_SEG_FIT ? c : c / kNsl);
+  }
+  if (p != len) return HDA_E_INVAL;
+  if (seg) {
+    if ((uint64_t)bitmap != want_bitmap) return HDA_E_INVAL;
+    for (uint32_t st : stamp)
+      if (st == 0u) return HDA_E_INVAL;  // a free block in no list
+  } else if (bitmap != 0) {
+    return HDA_E_INVAL;
+  }
+  if ((uint64_t)nf > h->cap || (uint64_t)nl > h->cap) return HDA_E_NOMETA;
+  // the device image
+  img.assign(heap_bytes(h->cap, h->cap), 0);
+  HeapHdr hdr;
+  std::memset(&hdr, 0, sizeof(hdr));
+  hdr.F = (uint32_t)nf;
+  hdr.L = (uint32_t)nl;
+  hdr.ag = (uint32_t)((uint64_t)A >> shift);
+  hdr.shift = shift;
+  hdr.rover = algo == HDA_NEXT_FIT ? (uint32_t)((uint64_t)rover >> shift) : 0u;
+  hdr.clock = clock;
+  hdr.algo = algo;
+  hdr.arena = A;
+  hdr.cf = h->cap;
+  hdr.cl = h->cap;
+  Ent* fe = reinterpret_cast<Ent*>(img.data() + sizeof(HeapHdr));
+  uint32_t* fst = reinterpret_cast<uint32_t*>(img.data() + sizeof(HeapHdr) + (size_t)h->cap * 8);
+  Ent* le = reinterpret_cast<Ent*>(img.data() + sizeof(HeapHdr) + (size_t)h->cap * 12);
+  for (int64_t i = 0; i < nf; ++i) {
+    const uint32_t a = (uint32_t)((uint64_t)fr[i].a >> shift), sg = (uint32_t)((uint64_t)fr[i].s >> shift);
+    fe[i] = ((uint64_t)sg << 32) | a;
+    fst[i] = stamp[i];
+    if (algo == HDA_SEG_FIT) hdr.cnt[floor_log2_u64((uint64_t)fr[i].s)]++;
+  }
+  for (int64_t i = 0; i < nl; ++i)
+    le[i] = ((uint64_t)((uint64_t)lv[i].s >> shift) << 32) | (uint32_t)((uint64_t)lv[i].a >> shift);
+  std::memcpy(img.data(), &hdr, sizeof(hdr));
   return HDA_OK;
 }
 
@@ -119,9 +313,13 @@ int hda_heap_create(uint64_t arena_bytes, uint64_t align, int algo, uint32_t met
   hda_heap* h = new (std::nothrow) hda_heap;
   if (!h) { g_held.fetch_sub((int64_t)bytes); return HDA_E_DEVICE; }
   h->bytes = bytes;
-  if (hipMalloc(&h->dev, bytes) != hipSuccess ||
-      hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
-    if (h->dev) (void)hipFree(h->dev);
+  h->algo = algo;
+  h->arena = arena_bytes;
+  h->align = align;
+  h->cap = cap;
+  h->stream = lib_stream();
+  h->dev = h->stream ? static_cast<HeapHdr*>(dev_alloc(bytes)) : nullptr;
+  if (!h->dev) {
     g_held.fetch_sub((int64_t)bytes);
     delete h;
     return HDA_E_DEVICE;
@@ -135,7 +333,8 @@ int hda_heap_create(uint64_t arena_bytes, uint64_t align, int algo, uint32_t met
   hdr.cf = cap;
   hdr.cl = cap;
   int64_t dummy = 0;
-  if (hipMemcpy(h->dev, &hdr, sizeof(hdr), hipMemcpyHostToDevice) != hipSuccess ||
+  if (hipMemcpyAsync(h->dev, &hdr, sizeof(hdr), hipMemcpyHostToDevice, h->stream) !=
+          hipSuccess ||
       call(h, kOpInit, 0, &dummy, nullptr, 0, nullptr) != HDA_OK) {
     hda_heap_destroy(h);
     return HDA_E_DEVICE;
@@ -147,9 +346,8 @@ int hda_heap_create(uint64_t arena_bytes, uint64_t align, int algo, uint32_t met
 int hda_heap_destroy(hda_heap* h) {
   if (!h) return HDA_E_INVAL;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
-  if (h->dev) (void)hipFree(h->dev);
-  if (h->io) (void)hipFree(h->io);
-  if (h->stream) (void)hipStreamDestroy(h->stream);
+  dev_free(h->dev);
+  dev_free(h->io);
   g_held.fetch_sub((int64_t)h->bytes);
   delete h;
   return HDA_OK;
@@ -174,6 +372,30 @@ int hda_free_partial(hda_heap* h, int64_t offset) {
   int64_t r = 0;
   const int rc = call(h, kOpFreePartial, offset, &r, nullptr, 0, nullptr);
   return rc != HDA_OK ? rc : (int)r;
+}
+
+int hda_heap_load(hda_heap* h, const int64_t* buf, size_t len) {
+  if (!h || (len && !buf)) return HDA_E_INVAL;
+  std::vector<uint8_t> img;
+  const int rc = build_image(h, buf, len, img);
+  if (rc != HDA_OK) return rc;
+  std::lock_guard<std::mutex> g(h->mu);
+  if (hipMemcpyAsync(h->dev, img.data(), img.size(), hipMemcpyHostToDevice, h->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    return HDA_E_DEVICE;
+  return HDA_OK;
+}
+
+int hda_set_device_allocator(hda_dev_alloc_fn alloc, hda_dev_free_fn release, void* ctx) {
+  if ((alloc == nullptr) != (release == nullptr)) return HDA_E_INVAL;
+  Allocator& a = allocator();
+  std::lock_guard<std::mutex> g(a.mu);
+  if (a.held != 0) return HDA_E_BUSY;  // buffers of the current allocator are still held
+  a.alloc = alloc;
+  a.release = release;
+  a.ctx = ctx;
+  return HDA_OK;
 }
 
 int hda_heap_state(const hda_heap* h, int64_t* buf, size_t cap, size_t* len) {

@@ -19,6 +19,7 @@
 #include "hda_wave.h"
 #include "hda_core.h"
 #include "hda_replay_body.h"
+#include "hda_mem.h"
 
 using namespace hda;
 
@@ -557,7 +558,8 @@ int hda_replay_autotune(const hda_batch_desc* d, int32_t sample_heaps, void* str
   int rc = HDA_E_DEVICE;
   float best = -1.0f;
   hda_tuning pick = ok[0];
-  if (hipMalloc(&buf, bytes) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
+  buf = static_cast<uint8_t*>(dev_alloc(bytes));
+  if (buf && hipEventCreate(&e0) == hipSuccess &&
       hipEventCreate(&e1) == hipSuccess &&
       hipMemcpyAsync(buf + o_arena, s_arena.data(), S * 8, hipMemcpyHostToDevice, s) ==
           hipSuccess &&
@@ -603,7 +605,7 @@ int hda_replay_autotune(const hda_batch_desc* d, int32_t sample_heaps, void* str
   if (e1) (void)hipEventDestroy(e1);
   if (buf) {
     (void)hipStreamSynchronize(s);
-    (void)hipFree(buf);
+    dev_free(buf);
   }
   if (rc != HDA_OK) return rc;
   hda_batch_desc dp = *d;

@@ -31,6 +31,7 @@
 #include "hda_wave.h"
 #include "hda_core.h"
 #include "hda_heap_dev.h"
+#include "hda_mem.h"
 
 using namespace hda;
 
@@ -324,11 +325,11 @@ int hda_serve_start(const hda_serve_config* cfg, hda_server** out) {
   const size_t ring_total = s->ring_bytes * (size_t)s->G;
   if (hipHostMalloc((void**)&s->rings, ring_total, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
       hipHostMalloc((void**)&s->stop, 256, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
-      hipMalloc((void**)&s->pool, s->slot_bytes * (size_t)c.max_heaps) != hipSuccess ||
+      !(s->pool = static_cast<uint8_t*>(dev_alloc(s->slot_bytes * (size_t)c.max_heaps))) ||
       hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
     if (s->rings) (void)hipHostFree(s->rings);
     if (s->stop) (void)hipHostFree(s->stop);
-    if (s->pool) (void)hipFree(s->pool);
+    dev_free(s->pool);
     return HDA_E_DEVICE;
   }
   std::memset(s->rings, 0, ring_total);
@@ -411,7 +412,7 @@ int hda_serve_stop(hda_server* s) {
   __atomic_store_n(s->stop, 1u, __ATOMIC_RELEASE);
   const hipError_t e = hipStreamSynchronize(s->stream);
   (void)hipStreamDestroy(s->stream);
-  (void)hipFree(s->pool);
+  dev_free(s->pool);
   (void)hipHostFree(s->rings);
   (void)hipHostFree(s->stop);
   delete s;

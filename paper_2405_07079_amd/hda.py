@@ -1,6 +1,9 @@
 """ctypes binding of ``libhda.so`` (the gfx950 library declared in
 ``include/hda.h``).  Argument marshalling only: every allocator step runs in
-the library's kernels.  PyTorch provides the device buffers and the stream.
+the library's kernels.  PyTorch provides the device buffers and the stream,
+and -- through ``hda_set_device_allocator``, installed when the library is
+loaded -- the device memory the library keeps for itself (torch's caching
+allocator).
 
 Importing this module does not load the library; the first call does, and it
 raises if ``libhda.so`` has not been built -- there is no CPU fallback.
@@ -94,8 +97,28 @@ HDA_OP_ALLOC, HDA_OP_FREE = 1, 2
 
 _lib = None
 
-EXPORTS = ["hda_replay_workspace", "hda_replay_resolve", "hda_replay",
-           "hda_replay_per_heap", "hda_replay_autotune", "hda_replay_capture",
+DEV_ALLOC = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+DEV_FREE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def _torch_alloc(nbytes, ctx):
+    import torch
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device())
+    except Exception:       # out of memory: the library reports HDA_E_DEVICE
+        return None
+
+
+def _torch_free(ptr, ctx):
+    import torch
+    torch.cuda.caching_allocator_delete(ptr)
+
+
+# kept alive for as long as the library may call them
+_TORCH_ALLOCATOR = (DEV_ALLOC(_torch_alloc), DEV_FREE(_torch_free))
+
+EXPORTS = ["hda_set_device_allocator", "hda_heap_load",
+           "hda_replay_workspace", "hda_replay_resolve", "hda_replay", "hda_replay_per_heap", "hda_replay_autotune", "hda_replay_capture",
            "hda_graph_launch", "hda_graph_destroy", "hda_bitmap_workspace", "hda_bitmap_replay",
            "hda_heap_create", "hda_heap_destroy", "hda_alloc",
            "hda_free", "hda_free_partial", "hda_heap_state", "hda_set_meta_budget", "hda_strerror",
@@ -144,6 +167,10 @@ def lib():
         L.hda_free.argtypes = [vp, ctypes.c_int64]
         L.hda_free_partial.restype = ctypes.c_int
         L.hda_free_partial.argtypes = [vp, ctypes.c_int64]
+        L.hda_heap_load.restype = ctypes.c_int
+        L.hda_heap_load.argtypes = [vp, vp, ctypes.c_size_t]
+        L.hda_set_device_allocator.restype = ctypes.c_int
+        L.hda_set_device_allocator.argtypes = [DEV_ALLOC, DEV_FREE, vp]
         L.hda_heap_state.restype = ctypes.c_int
         L.hda_heap_state.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
         L.hda_set_meta_budget.restype = ctypes.c_int64
@@ -167,7 +194,29 @@ def lib():
             fn.restype = ctypes.c_int
             fn.argtypes = args
         _lib = L
+        if torch_available():
+            use_torch_allocator()
     return _lib
+
+
+def torch_available() -> bool:
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def use_torch_allocator() -> None:
+    """Route the library's own device buffers through torch's caching
+    allocator (done when the library is loaded on a machine with a GPU)."""
+    _check(lib().hda_set_device_allocator(*_TORCH_ALLOCATOR, None), "hda_set_device_allocator")
+
+
+def use_hip_allocator() -> None:
+    """Back to hipMalloc / hipFree for the library's own device buffers."""
+    _check(lib().hda_set_device_allocator(DEV_ALLOC(), DEV_FREE(), None),
+           "hda_set_device_allocator")
 
 
 def strerror(code: int) -> str:
@@ -427,6 +476,11 @@ class Heap:
 
     def free_partial(self, offset: int) -> int:
         return int(lib().hda_free_partial(self._h, int(offset)))
+
+    def load(self, state) -> int:
+        """Resume from a canonical state; returns the status code."""
+        st = np.ascontiguousarray(state, np.int64)
+        return int(lib().hda_heap_load(self._h, st.ctypes.data if st.size else None, st.size))
 
     def state(self) -> np.ndarray:
         n = ctypes.c_size_t(0)

@@ -43,3 +43,12 @@ def test_header_compiles_as_c_and_cpp():
     hdr = os.path.join(ROOT, "include", "hda.h")
     for lang, cc in (("c", "gcc"), ("c++", "g++")):
         subprocess.check_call([cc, "-fsyntax-only", "-Wall", "-Werror", "-x", lang, hdr])
+
+
+def test_device_allocator_needs_both_callbacks():
+    """Exactly one callback is an invalid argument (no GPU call is made)."""
+    L = hda.lib()
+    rc = L.hda_set_device_allocator(hda._TORCH_ALLOCATOR[0], hda.DEV_FREE(), None)
+    assert rc == hda.HDA_E_INVAL
+    rc = L.hda_set_device_allocator(hda.DEV_ALLOC(), hda._TORCH_ALLOCATOR[1], None)
+    assert rc == hda.HDA_E_INVAL

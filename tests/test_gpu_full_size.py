@@ -1,18 +1,20 @@
 """Full-size workloads on the GPU, in the launch configuration the benchmark
-uses, checked on heaps the oracle replays one by one (and, for the service,
-on properties that hold at any size).
+uses, compared with the oracle on EVERY heap: every result and every final
+state, element by element (the oracle replays the whole batch on all host
+threads).
 
 * 4,096 heaps x 100,000 requests (16 MiB arenas), best fit, segregated
-  fit and TLSF, default tuning, states dumped: 24 sampled heaps per algorithm
-  (including the first and the last) compared element by element.
+  fit and TLSF, default tuning, states dumped.
 * The same batch on best fit with 2 % of the frees partial, and replayed by
-  the bitmask allocator: 24 sampled heaps each.
+  the bitmask allocator.
 * The uneven batch (16,384 heaps, 46.9 M requests), autotuned and launched
-  as a captured graph: 48 sampled heaps plus the 4 longest.
+  as a captured graph.
 * The service under 1e7 requests/s from 100,000 clients (one heap each):
   every request completes without error, throughput follows the offered
-  rate, p50 latency is finite.
+  rate, p99 latency within the stated bound.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -23,24 +25,46 @@ from paper_2405_07079_amd import workloads as W
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
+# the service's stated latency bound at 1e7 requests/s from 100,000 clients
+P99_BOUND_US = 200.0
+
 
 def say(*a):
     print(*a, flush=True)
 
 
-def check_heaps(batch, res, db, status, heaps):
-    states = dict(zip(heaps, hda.states_to_host(db, heaps)))
-    sub = batch.subset(heaps)
-    ores, ostates, _ = oracle.replay_batch(sub, threads=16)
-    for k, h in enumerate(heaps):
-        a, b = batch.req_off[h], batch.req_off[h + 1]
-        got, exp = res[a:b], ores[sub.req_off[k]:sub.req_off[k + 1]]
-        if not np.array_equal(got, exp):
-            i = int(np.nonzero(got != exp)[0][0])
-            raise AssertionError(f"heap {h} algo {batch.algo[h]} request {i}: "
-                                 f"gpu {got[i]} oracle {exp[i]}")
-        assert status[h] == 0, (h, status[h])
-        assert np.array_equal(states[h], ostates[k]), f"heap {h} state"
+def host_threads():
+    try:
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except AttributeError:
+        return 8
+
+
+def check_every_heap(batch, db, state_blocks):
+    """Results, statuses and states of all heaps against the oracle."""
+    res = db.res[:batch.requests].cpu().numpy()
+    status = db.status.cpu().numpy()
+    so = db.state_off.cpu().numpy()
+    sl = db.state_len.cpu().numpy()
+    state = db.state.cpu().numpy()
+    say(f"  oracle: {batch.heaps} heaps, {batch.requests} requests, "
+        f"{host_threads()} threads")
+    ores, ostates, _ = oracle.replay_batch(batch, threads=host_threads(),
+                                           state_blocks=state_blocks)
+    bad = np.nonzero(status != 0)[0]
+    assert bad.size == 0, f"heap {bad[0]} status {status[bad[0]]}"
+    if not np.array_equal(res, ores):
+        i = int(np.nonzero(res != ores)[0][0])
+        h = int(np.searchsorted(batch.req_off, i, side="right") - 1)
+        raise AssertionError(f"heap {h} (algo {batch.algo[h]}) request "
+                             f"{i - batch.req_off[h]}: gpu {res[i]} oracle {ores[i]}")
+    for h in range(batch.heaps):
+        got = state[so[h]:so[h] + min(sl[h], so[h + 1] - so[h])]
+        assert np.array_equal(got, ostates[h]), f"heap {h} (algo {batch.algo[h]}) state"
+    say(f"  {batch.heaps} heaps equal the oracle")
+
+
+META_FREE, META_LIVE = 4096, 8192
 
 
 @pytest.fixture(scope="module")
@@ -49,65 +73,41 @@ def batch_4096():
 
 
 @pytest.mark.parametrize("algo", (W.BEST_FIT, W.SEG_FIT, W.TLSF))
-def test_4096_heaps_full_size_sampled(batch_4096, algo):
+def test_4096_heaps_full_size(batch_4096, algo):
     b = batch_4096.with_algo(algo)
     say(f"case: 4096 x 16 MiB heaps, 100k requests each, algo {algo}")
-    db = hda.upload(b)
+    db = hda.upload(b, meta_free=META_FREE, meta_live=META_LIVE)
     hda.hda_replay(db)
     torch.cuda.synchronize()
-    status = db.status.cpu().numpy()
-    assert (status == 0).all()
-    rng = np.random.default_rng(100 + algo)
-    heaps = sorted(set(rng.choice(b.heaps, 22, replace=False).tolist()) | {0, b.heaps - 1})
-    res = np.empty(b.requests, np.int64)
-    for h in heaps:   # copy only the sampled heaps' results back
-        a, e = int(b.req_off[h]), int(b.req_off[h + 1])
-        res[a:e] = db.res[a:e].cpu().numpy()
-    check_heaps(b, res, db, status, heaps)
+    check_every_heap(b, db, META_FREE + META_LIVE)
 
 
-def test_4096_heaps_bitmap_full_size_sampled(batch_4096):
+def test_4096_heaps_bitmap_full_size(batch_4096):
     """The benchmark's bitmask-allocator leg: the same batch, one flag per
-    granule; 24 sampled heaps element by element."""
+    granule."""
     b = batch_4096.with_algo(W.BITMAP)
     say("case: 4096 x 16 MiB heaps, 100k requests each, bitmask allocator")
-    db = hda.upload(b)
+    db = hda.upload(b, meta_live=META_LIVE)
     hda.hda_bitmap_replay(db, hda.max_granules(b))
     torch.cuda.synchronize()
-    status = db.status.cpu().numpy()
-    assert (status == 0).all()
-    rng = np.random.default_rng(55)
-    heaps = sorted(set(rng.choice(b.heaps, 22, replace=False).tolist()) | {0, b.heaps - 1})
-    res = np.empty(b.requests, np.int64)
-    for h in heaps:
-        a, e = int(b.req_off[h]), int(b.req_off[h + 1])
-        res[a:e] = db.res[a:e].cpu().numpy()
-    check_heaps(b, res, db, status, heaps)
+    check_every_heap(b, db, 2 * META_LIVE + 1)
 
 
-def test_4096_heaps_partial_frees_full_size_sampled():
+def test_4096_heaps_partial_frees_full_size():
     """The benchmark's partial-deallocation leg: best fit, 2 % of the frees
-    partial, default tuning; 24 sampled heaps element by element."""
+    partial, default tuning."""
     b = W.uniform_batch(algo=W.BEST_FIT, p_partial=0.02)
     say("case: 4096 x 16 MiB heaps, 100k requests each, best fit, 2 % partial frees")
-    db = hda.upload(b)
+    db = hda.upload(b, meta_free=META_FREE, meta_live=META_LIVE)
     hda.hda_replay(db)
     torch.cuda.synchronize()
-    status = db.status.cpu().numpy()
-    assert (status == 0).all()
-    rng = np.random.default_rng(77)
-    heaps = sorted(set(rng.choice(b.heaps, 22, replace=False).tolist()) | {0, b.heaps - 1})
-    res = np.empty(b.requests, np.int64)
-    for h in heaps:
-        a, e = int(b.req_off[h]), int(b.req_off[h + 1])
-        res[a:e] = db.res[a:e].cpu().numpy()
-    check_heaps(b, res, db, status, heaps)
+    check_every_heap(b, db, META_FREE + META_LIVE)
 
 
 def test_uneven_batch_full_size_autotuned_graph():
     b = W.uneven_batch()
     say(f"case: uneven batch, {b.heaps} heaps, {b.requests} requests, autotuned, graph")
-    db = hda.upload(b)
+    db = hda.upload(b, meta_free=META_FREE, meta_live=META_LIVE)
     hda.retune(db, hda.hda_replay_autotune(db))
     g = hda.ReplayGraph(db)
     try:
@@ -116,14 +116,7 @@ def test_uneven_batch_full_size_autotuned_graph():
         torch.cuda.synchronize()
     finally:
         g.close()
-    status = db.status.cpu().numpy()
-    assert (status == 0).all()
-    res = db.res.cpu().numpy()[:b.requests]
-    lens = np.diff(b.req_off)
-    rng = np.random.default_rng(7)
-    heaps = sorted(set(rng.choice(b.heaps, 48, replace=False).tolist())
-                   | set(np.argsort(-lens)[:4].tolist()))
-    check_heaps(b, res, db, status, heaps)
+    check_every_heap(b, db, META_FREE + META_LIVE)
 
 
 def test_service_at_full_load():
@@ -138,4 +131,5 @@ def test_service_at_full_load():
     assert rep["completed"] == rep["issued"] > 5_000_000
     assert rep["throughput"] > 0.9e7
     assert 0 < rep["p50_us"] <= rep["p99_us"] <= rep["max_us"]
+    assert rep["p99_us"] <= P99_BOUND_US, f"p99 {rep['p99_us']:.0f} us over the stated bound"
     assert rep["alloc_ok"] > 0 and rep["frees"] > 0

@@ -156,3 +156,147 @@ def test_paper_analog_trace_matches_oracle():
     exp, _ = oracle.replay_heap(int(b.algo[0]), int(b.arena[0]), int(b.align[0]), req)
     assert np.array_equal(res, exp)
     assert (lat[req >= 0] > 0).all()
+
+
+# ---------------------------------------------------------------------------
+# Resuming a heap from a canonical state (hda_heap_load)
+# ---------------------------------------------------------------------------
+
+def drive(gh, oh, ops):
+    """Apply (kind, value) ops to a GPU heap and its oracle twin: ("a", size)
+    allocates, ("f", draw) frees the oracle's live[(draw * L) >> 32]."""
+    out = []
+    for kind, v in ops:
+        if kind == "a":
+            r = gh.alloc(v)
+            assert r == oh.alloc(v)
+        else:
+            live = oracle.parse_state(oh.state(), oh.algo)["live"]
+            if not live:
+                out.append(None)
+                continue
+            x = live[(v * len(live)) >> 32][0]
+            r = gh.free(x)
+            assert r == oh.free(x) == 0
+        out.append(r)
+    return out
+
+
+def random_ops(seed, n, hi=3000):
+    rng = np.random.default_rng(seed)
+    return [("a", int(rng.integers(0, hi))) if rng.random() < 0.6
+            else ("f", int(rng.integers(0, 1 << 32))) for _ in range(n)]
+
+
+@pytest.mark.parametrize("algo", (0, 1, 2, 3, 4))
+def test_load_resumes_the_heap(algo):
+    """Run k calls, dump, load the dump into a fresh heap and continue: every
+    result and the final state equal an uninterrupted oracle run."""
+    print(f"case: heap load, algo {algo}", flush=True)
+    A, g = 1 << 16, 32
+    ops = random_ops(70 + algo, 500)
+    oh = oracle.Heap(algo, A, g)                 # uninterrupted
+    first = hda.Heap(A, g, algo, meta_cap=512)
+    drive(first, oh, ops[:250])
+    dumped = first.state()
+    assert np.array_equal(dumped, oh.state())
+    first.close()
+    second = hda.Heap(A, g, algo, meta_cap=512)
+    assert second.load(dumped) == hda.HDA_OK
+    assert np.array_equal(second.state(), dumped)
+    drive(second, oh, ops[250:])
+    assert np.array_equal(second.state(), oh.state())
+    second.close()
+
+
+@pytest.mark.parametrize("algo", (0, 1, 2, 3, 4))
+def test_load_a_replayed_state(algo):
+    """A state the oracle reached by replaying a trace of the benchmark's
+    shape (16 MiB, hundreds of blocks) is loaded into a GPU heap; both then
+    continue with the same calls."""
+    from paper_2405_07079_amd import workloads as W
+    print(f"case: load a replayed state, algo {algo}", flush=True)
+    b = W.uniform_batch(seed=2, heaps=1, n=6000, algo=algo)
+    A, g = int(b.arena[0]), int(b.align[0])
+    oh = oracle.Heap(algo, A, g)
+    oh.replay(b.req)
+    gh = hda.Heap(A, g, algo, meta_cap=4096)
+    assert gh.load(oh.state()) == hda.HDA_OK
+    drive(gh, oh, random_ops(90 + algo, 400, hi=1 << 20))
+    assert np.array_equal(gh.state(), oh.state())
+    gh.close()
+
+
+def malformed(state, algo):
+    """(name, bad state) pairs derived from a valid canonical state."""
+    st = [int(x) for x in state]
+    p = oracle.parse_state(st, algo)
+    nf, nl = len(p["free"]), len(p["live"])
+    out = [("truncated", st[:-1]), ("extra word", st + [0])]
+    if nf >= 2:
+        s2 = list(st)
+        s2[1], s2[3] = s2[3], s2[1]                      # free blocks out of order
+        out.append(("free order", s2))
+    if nl >= 1:
+        s2 = list(st)
+        s2[2 + 2 * nf + 1] += 16                         # first live block moved: overlap
+        out.append(("overlap", s2))
+        s2 = list(st)
+        s2[2 + 2 * nf + 2] += 1                          # unaligned size
+        out.append(("unaligned", s2))
+    rover_at = 2 + 2 * nf + 2 * nl
+    s2 = list(st)
+    s2[rover_at] = 12345 if algo == 1 else 0
+    out.append(("rover", s2))
+    if algo in (3, 4):
+        s2 = list(st)
+        s2[rover_at + 1] ^= 1 << 62                      # bitmap disagrees with the lists
+        out.append(("bitmap", s2))
+    return out
+
+
+@pytest.mark.parametrize("algo", (0, 1, 2, 3, 4))
+def test_load_rejects_malformed_states(algo):
+    print(f"case: heap load of malformed states, algo {algo}", flush=True)
+    A, g = 1 << 16, 32
+    oh = oracle.Heap(algo, A, g)
+    src = hda.Heap(A, g, algo, meta_cap=512)
+    drive(src, oh, random_ops(110 + algo, 120))
+    good = src.state()
+    src.close()
+    gh = hda.Heap(A, g, algo, meta_cap=512)
+    gh.alloc(96)
+    before = gh.state()
+    for name, bad in malformed(good, algo):
+        assert gh.load(np.array(bad, np.int64)) == hda.HDA_E_INVAL, name
+        assert np.array_equal(gh.state(), before), name
+    # a state of another arena, alignment or algorithm
+    other = hda.Heap(A * 2, g, algo, meta_cap=512)
+    assert other.load(good) == hda.HDA_E_INVAL
+    other.close()
+    # more blocks than the tables hold
+    small = hda.Heap(A, g, algo, meta_cap=64)
+    p = oracle.parse_state(good, algo)
+    if max(len(p["free"]), len(p["live"])) > 64:
+        assert small.load(good) == hda.HDA_E_NOMETA
+    small.close()
+    gh.close()
+
+
+def test_library_memory_comes_from_torch():
+    """The library's own device buffers are taken from torch's caching
+    allocator (installed by the binding) and given back on release; the
+    allocator cannot be swapped while they are held."""
+    import torch
+    print("case: device allocator", flush=True)
+    torch.cuda.synchronize()
+    m0 = torch.cuda.memory_allocated()
+    gh = hda.Heap(1 << 20, 64, 3, meta_cap=4096)
+    m1 = torch.cuda.memory_allocated()
+    assert m1 - m0 >= 4096 * 20          # free table, stamps and live table
+    with pytest.raises(hda.HdaError) as e:
+        hda.use_hip_allocator()
+    assert e.value.code == hda.HDA_E_BUSY
+    assert gh.alloc(1000) == 0
+    gh.close()
+    assert torch.cuda.memory_allocated() == m0

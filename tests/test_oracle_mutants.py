@@ -74,12 +74,20 @@ MUTANTS = [
     ("bm_left_part_dropped", "if (p > a) fl[a] = p - a;", "", 0, "bitmap"),
     ("bm_rover_at_start", "rover = p + s;\n        return p;", "rover = p;\n        return p;", 0,
      "bitmap"),
+    # instrumentation counters (checked by their own pin file)
+    ("ff_examined_not_counted", "                ++examined;\n                if (it->second >= s) { pick = it; break; }",
+     "                if (it->second >= s) { pick = it; break; }", 0, "counters"),
+    ("bf_examined_past_exact", "if (it->second == s) break;", "", 0, "counters"),
+    ("sf_push_old_head_not_counted",
+     "if (head[c] != NIL) { ht.at(head[c]).prev_free = a; ++touched; }",
+     "if (head[c] != NIL) { ht.at(head[c]).prev_free = a; }", 0, "counters"),
 ]
 
 PINS = {"seq": [os.path.join(ROOT, "tests", f)
                 for f in ("test_oracle_pins.py", "test_oracle_partial.py")],
         "tlsf": [os.path.join(ROOT, "tests", "test_oracle_tlsf.py")],
-        "bitmap": [os.path.join(ROOT, "tests", "test_oracle_bitmap.py")]}
+        "bitmap": [os.path.join(ROOT, "tests", "test_oracle_bitmap.py")],
+        "counters": [os.path.join(ROOT, "tests", "test_oracle_counters.py")]}
 
 
 def _replace_nth(text, old, new, n):
