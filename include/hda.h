@@ -188,6 +188,23 @@ int hda_bitmap_replay(const hda_batch_desc *d, uint64_t max_granules, void *stre
  * meta_free, meta_live and tuning).  Returns 0 on invalid arguments. */
 size_t hda_replay_workspace(const hda_batch_desc *d);
 
+/* hda_replay for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid allocation):
+ * the same replay, but the scratch it needs lives in a device array of
+ * HDA_STATIC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends; d->workspace and d->workspace_bytes are ignored.
+ * Nothing is allocated or freed (no hipMalloc / hipFree, no allocator
+ * callback).  HDA_E_RANGE when hda_replay_workspace(d) exceeds
+ * HDA_STATIC_SCRATCH_BYTES (fewer heaps per call, smaller meta_free /
+ * meta_live, or fewer persistent groups bring it down); HDA_E_INVAL /
+ * HDA_E_DEVICE as for hda_replay.  Every call on one GPU uses that GPU's one
+ * array, which keeps the last call's contents: calls whose work overlaps on
+ * one GPU (on different streams, or from different threads) race and must
+ * not be made; calls in sequence on one stream are fine.  Asynchronous on
+ * `stream`; the caller's buffers in `d` as for hda_replay. */
+#define HDA_STATIC_SCRATCH_BYTES (64u << 20)
+int hda_replay_static(const hda_batch_desc *d, void *stream);
+
 /* Resolve the tuning actually used for `d` (autotuned defaults filled in). */
 int hda_replay_resolve(const hda_batch_desc *d, hda_tuning *out);
 

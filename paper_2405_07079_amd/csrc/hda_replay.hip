@@ -615,6 +615,56 @@ int hda_replay_autotune(const hda_batch_desc* d, int32_t sample_heaps, void* str
 
 }  // extern "C"
 
+// ---- replay without allocation ----
+//
+// The device scratch of hda_replay_static: one array per GPU the library
+// runs on, held until the process ends.  Its name is a host-side stand-in in
+// host code; kernels are only ever given the device address that
+// hipGetSymbolAddress returns for the current device.
+namespace {
+constexpr size_t kStaticScratchBytes = size_t(HDA_STATIC_SCRATCH_BYTES);
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+// The scratch's device address on the current device, looked up once per
+// device (with that device current); nullptr if the lookup fails.
+uint8_t* static_scratch() {
+  static std::mutex mu;
+  static std::vector<uint8_t*> ptrs;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return nullptr;
+  std::lock_guard<std::mutex> g(mu);
+  if ((int)ptrs.size() <= dev) ptrs.resize(dev + 1, nullptr);
+  if (!ptrs[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    ptrs[dev] = static_cast<uint8_t*>(ptr);
+  }
+  return ptrs[dev];
+}
+}  // namespace
+
+extern "C" {
+
+int hda_replay_static(const hda_batch_desc* d, void* stream) {
+  Plan pl;
+  if (!desc_ok(d) || !make_plan(d, true, &pl)) return HDA_E_INVAL;
+  if (d->n_heaps == 0) return HDA_OK;
+  if (pl.bytes > kStaticScratchBytes) return HDA_E_RANGE;
+  uint8_t* ws = static_scratch();
+  if (!ws) return HDA_E_DEVICE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!set_lds_attrs(pl)) return HDA_E_DEVICE;
+  // the same launches as hda_replay, with the scratch as their workspace;
+  // the classify kernel clears the queue counters (no memset), and every
+  // spill entry is written before it is read
+  hda_batch_desc dd = *d;
+  dd.workspace = ws;
+  dd.workspace_bytes = kStaticScratchBytes;
+  return enqueue(&dd, pl, s);
+}
+
+}  // extern "C"
+
 struct hda_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;

@@ -118,7 +118,7 @@ def _torch_free(ptr, ctx):
 _TORCH_ALLOCATOR = (DEV_ALLOC(_torch_alloc), DEV_FREE(_torch_free))
 
 EXPORTS = ["hda_set_device_allocator", "hda_heap_load",
-           "hda_replay_workspace", "hda_replay_resolve", "hda_replay", "hda_replay_per_heap", "hda_replay_autotune", "hda_replay_capture",
+           "hda_replay_workspace", "hda_replay_resolve", "hda_replay", "hda_replay_static", "hda_replay_per_heap", "hda_replay_autotune", "hda_replay_capture",
            "hda_graph_launch", "hda_graph_destroy", "hda_bitmap_workspace", "hda_bitmap_replay",
            "hda_heap_create", "hda_heap_destroy", "hda_alloc",
            "hda_free", "hda_free_partial", "hda_heap_state", "hda_set_meta_budget", "hda_strerror",
@@ -146,6 +146,8 @@ def lib():
         L.hda_replay_resolve.argtypes = [D, ctypes.POINTER(hda_tuning)]
         L.hda_replay.restype = ctypes.c_int
         L.hda_replay.argtypes = [D, vp]
+        L.hda_replay_static.restype = ctypes.c_int
+        L.hda_replay_static.argtypes = [D, vp]
         L.hda_replay_per_heap.restype = ctypes.c_int
         L.hda_replay_per_heap.argtypes = [D, vp]
         L.hda_replay_autotune.restype = ctypes.c_int
@@ -352,6 +354,17 @@ def hda_replay_resolve(db: DeviceBatch) -> dict:
 def hda_replay(db: DeviceBatch, stream=None) -> None:
     """Enqueue the batched replay on `stream` (default: torch's current)."""
     _check(lib().hda_replay(ctypes.byref(db.desc()), _stream_ptr(stream)), "hda_replay")
+
+
+# bytes of the library's own per-GPU scratch behind hda_replay_static
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def hda_replay_static(db: DeviceBatch, stream=None) -> None:
+    """Enqueue the batched replay on `stream` with the library's static
+    per-GPU scratch instead of the batch's workspace (no allocation)."""
+    _check(lib().hda_replay_static(ctypes.byref(db.desc()), _stream_ptr(stream)),
+           "hda_replay_static")
 
 
 def max_granules(batch) -> int:
