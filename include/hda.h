@@ -141,6 +141,11 @@ typedef struct hda_tuning {
   int32_t lds_free;        /* free-table entries in LDS per heap (mult. of 64) */
   int32_t lds_live;        /* live-table entries in LDS per heap (mult. of 64) */
   int32_t groups;          /* persistent workgroups (0 = fill the device)      */
+  int32_t heavy_heaps;     /* the first heavy_heaps heaps of the order are
+                              replayed by the ordered core in a launch of
+                              their own beside the others' (0 = none)          */
+  int32_t heavy_kib;       /* LDS pool per ordered-core heap, KiB (16 up to the
+                              device's LDS per workgroup; 0 = 64)             */
 } hda_tuning;
 
 typedef struct hda_batch_desc {

@@ -19,6 +19,7 @@
 #include "hda_wave.h"
 #include "hda_core.h"
 #include "hda_replay_body.h"
+#include "hda_ordered.h"
 #include "hda_mem.h"
 
 using namespace hda;
@@ -27,10 +28,11 @@ namespace {
 
 constexpr int kClasses = 2;  // heaps with valid parameters, and the others
 constexpr int kValid = 0, kInvalid = 1;
-// Queue words in the workspace: the heap queue, then the number of heaps
-// moved from the lean to the general core.
-constexpr int kQueueWords = 2;
+// Queue words in the workspace: the heap queue, the number of heaps moved
+// from the lean to the general core, and the queue of the ordered-core launch.
+constexpr int kQueueWords = 3;
 constexpr int kMigrated = 1;
+constexpr int kHeavyQueue = 2;
 
 struct ClassifyParams {
   const int64_t* arena;
@@ -100,15 +102,18 @@ __global__ void __launch_bounds__(1024) classify_kernel(ClassifyParams q) {
   }
 }
 
-// Persistent loop: waves pull heap positions from p.queue until the list is
-// used up; with use_queue = 0 wave `slot` takes list entry first + slot.
+// Persistent loop: waves pull list positions list_lo, list_lo + 1, ... from
+// p.queue until min(list_hi, the list's length) is reached; with use_queue =
+// 0 wave `slot` takes list entry first + slot.
 template <typename Fn>
 __device__ __forceinline__ void for_each_heap(const ReplayParams& p, uint64_t slot, Fn&& f) {
-  const int64_t n = p.use_queue ? (int64_t)*p.count : p.n_heaps;
   if (!p.use_queue) {
-    if ((int64_t)slot < n) f((int64_t)p.list[p.first + (int64_t)slot]);
+    if ((int64_t)slot < p.n_heaps) f((int64_t)p.list[p.first + (int64_t)slot]);
     return;
   }
+  const int64_t len = (int64_t)*p.count;
+  const int64_t hi = len < p.list_hi ? len : p.list_hi;
+  const int64_t n = hi - p.list_lo;
   // A wave can take at most every heap, so the loop is bounded even if the
   // queue were never to run dry.
   for (int64_t taken = 0; taken < n; ++taken) {
@@ -119,7 +124,7 @@ __device__ __forceinline__ void for_each_heap(const ReplayParams& p, uint64_t sl
     uint32_t hq = atomicAdd(p.queue, lane_id() == 0 ? 1u : 0u);
     hq = rdlane(hq, 0);
     if ((int64_t)hq >= n) break;
-    f((int64_t)p.list[hq]);
+    f((int64_t)p.list[p.list_lo + (int64_t)hq]);
   }
 }
 
@@ -173,6 +178,19 @@ __global__ void __launch_bounds__(1024) lean_kernel(ReplayParams p) {
       case kTlsf: lean_one_heap<kTlsf, RF>(p, lds, c, heap); break;
       default: reject_heap(p, heap); break;  // the bitmask allocator has its own kernel
     }
+  });
+}
+
+// Ordered core (hda_ordered.h) for the heaps taken first from the order: one
+// wave per workgroup owning the whole dynamic LDS of the launch as its pool,
+// and a device-memory slot per workgroup for what does not fit.
+__global__ void __launch_bounds__(64) ordered_kernel(ReplayParams p) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  HDA_LDS uint8_t* pool = (HDA_LDS uint8_t*)smem;
+  const uint64_t slot = blockIdx.x;
+  HDA_GLOBAL uint8_t* dev = (HDA_GLOBAL uint8_t*)(p.ord_dev + slot * p.ord_dev_stride);
+  for_each_heap(p, slot, [&](int64_t heap) __attribute__((always_inline)) {
+    ord_any_heap(p, pool, dev, heap);
   });
 }
 
@@ -235,6 +253,13 @@ struct Plan {
   bool lean;
   uint32_t capF, capL;
   Pass main;
+  // the ordered-core launch: the first `heavy` heaps of the order, one wave
+  // per workgroup with a pool of heavy_pool LDS bytes, heavy_groups of them
+  int64_t heavy = 0;
+  uint32_t heavy_pool = 0, heavy_slot_bytes = 0;
+  int64_t heavy_groups = 0;
+  uint64_t heavy_stride = 0;
+  size_t off_ord = 0;
   size_t off_counts, off_queues, off_lists, bytes;
 };
 
@@ -263,7 +288,8 @@ bool make_plan(const hda_batch_desc* d, bool persistent, Plan* pl) {
   const KernelSet* set = find_set(rf);
   if (!set || tu.reg_live > 0) return false;
   if (tu.heaps_per_group < 0 || tu.heaps_per_group > 16 || (tu.lds_free > 0 && tu.lds_free % 64) ||
-      (tu.lds_live > 0 && tu.lds_live % 64) || tu.groups < 0)
+      (tu.lds_live > 0 && tu.lds_live % 64) || tu.groups < 0 || tu.heavy_heaps < 0 ||
+      tu.heavy_kib < 0)
     return false;
   const bool lean = rf > 0;
   uint32_t W = tu.heaps_per_group > 0 ? (uint32_t)tu.heaps_per_group : 4u;
@@ -300,8 +326,30 @@ bool make_plan(const hda_batch_desc* d, bool persistent, Plan* pl) {
   }
   m.lds_group = m.lds_wave * W;
   if (m.lds_group > dc->max_lds) return false;
-  m.groups = persistent ? occupancy_groups(set->fn, W, m.lds_group, dc->cus, tu.groups,
-                                           d->n_heaps)
+  // the ordered-core launch (persistent replays only)
+  const int64_t heavy = persistent ? std::min<int64_t>(tu.heavy_heaps, d->n_heaps) : 0;
+  int heavy_cus = 0;
+  if (heavy > 0) {
+    const uint32_t kib = tu.heavy_kib > 0 ? (uint32_t)tu.heavy_kib : 64u;
+    if (kib < 16u || (size_t)kib * 1024u > dc->max_lds) return false;
+    if (capF > kOrdMaxFree) return false;  // the ordered core holds at most this many
+    pl->heavy = heavy;
+    pl->heavy_pool = kib * 1024u;
+    // TLSF's list heads first, then half of the rest for chunk slots
+    pl->heavy_slot_bytes = (pl->heavy_pool - kOrdTlsfHeadBytes) / 2u;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)ordered_kernel, 64,
+                                                     (size_t)pl->heavy_pool) != hipSuccess ||
+        nb < 1)
+      nb = 1;
+    pl->heavy_groups = std::max<int64_t>(1, std::min<int64_t>(heavy, (int64_t)nb * dc->cus));
+    heavy_cus = (int)((pl->heavy_groups + nb - 1) / nb);
+    pl->heavy_stride = (ord_dev_bytes(capL) + 255) / 256 * 256;
+  }
+  // the other heaps fill the CUs the ordered-core launch leaves
+  const int light_cus = std::max(1, dc->cus - heavy_cus);
+  m.groups = persistent ? occupancy_groups(set->fn, W, m.lds_group, light_cus, tu.groups,
+                                           d->n_heaps - heavy)
                         : 1;
   m.slots = m.groups * W;
   pl->set = set;
@@ -317,6 +365,7 @@ bool make_plan(const hda_batch_desc* d, bool persistent, Plan* pl) {
   m.off_free = off; off = align_up(off + (size_t)m.slots * m.sf * 8);
   m.off_stamp = off; off = align_up(off + (size_t)m.slots * m.sf * 4);
   m.off_live = off; off = align_up(off + (size_t)m.slots * m.sl * 8);
+  pl->off_ord = off; off = align_up(off + (size_t)pl->heavy_groups * pl->heavy_stride);
   pl->bytes = off;
   return true;
 }
@@ -367,6 +416,23 @@ ReplayParams replay_params(const hda_batch_desc* d, const Plan& pl) {
   p.waves_per_group = ps.W;
   p.lds_wave_bytes = ps.lds_wave;
   p.use_queue = 1;
+  p.list_lo = pl.heavy;
+  p.list_hi = INT64_MAX;
+  return p;
+}
+
+// Parameters of the ordered-core launch: list positions [0, heavy), its own
+// queue counter, its device slots.
+ReplayParams heavy_params(const hda_batch_desc* d, const Plan& pl) {
+  ReplayParams p = replay_params(d, pl);
+  uint8_t* ws = static_cast<uint8_t*>(d->workspace);
+  p.queue = reinterpret_cast<uint32_t*>(ws + pl.off_queues) + kHeavyQueue;
+  p.list_lo = 0;
+  p.list_hi = pl.heavy;
+  p.ord_pool_bytes = pl.heavy_pool;
+  p.ord_slot_bytes = pl.heavy_slot_bytes;
+  p.ord_dev = ws + pl.off_ord;
+  p.ord_dev_stride = pl.heavy_stride;
   return p;
 }
 
@@ -376,7 +442,24 @@ bool set_lds_attr(const void* fn, uint32_t bytes) {
          hipSuccess;
 }
 
-bool set_lds_attrs(const Plan& pl) { return set_lds_attr(pl.set->fn, pl.main.lds_group); }
+bool set_lds_attrs(const Plan& pl) {
+  return set_lds_attr(pl.set->fn, pl.main.lds_group) &&
+         (pl.heavy == 0 || set_lds_attr((const void*)ordered_kernel, pl.heavy_pool));
+}
+
+// A second stream per device for the launch that runs beside the
+// ordered-core one (default priority, not blocking the null stream).
+hipStream_t fork_stream() {
+  static std::mutex mu;
+  static std::vector<hipStream_t> streams;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return nullptr;
+  std::lock_guard<std::mutex> g(mu);
+  if ((int)streams.size() <= dev) streams.resize(dev + 1, nullptr);
+  if (!streams[dev] && hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking) != hipSuccess)
+    streams[dev] = nullptr;
+  return streams[dev];
+}
 
 hipError_t launch(const void* fn, dim3 grid, dim3 block, uint32_t lds, hipStream_t st,
                   ReplayParams& p) {
@@ -390,15 +473,36 @@ int classify(const hda_batch_desc* d, const Plan& pl, hipStream_t s) {
   return hipGetLastError() == hipSuccess ? HDA_OK : HDA_E_DEVICE;
 }
 
-// Classify, then the persistent replay kernel, both on s.
+// Classify, then the persistent replay kernel, both on s.  With heaps for
+// the ordered core, their launch follows classify on s and the other heaps'
+// launch runs beside it on the fork stream, joined back to s by an event.
 int enqueue(const hda_batch_desc* d, const Plan& pl, hipStream_t s) {
   int rc = classify(d, pl, s);
   if (rc != HDA_OK) return rc;
   ReplayParams p = replay_params(d, pl);
-  if (launch(pl.set->fn, dim3((uint32_t)pl.main.groups), dim3(64 * pl.main.W),
-             pl.main.lds_group, s, p) != hipSuccess)
-    return HDA_E_DEVICE;
-  return hipGetLastError() == hipSuccess ? HDA_OK : HDA_E_DEVICE;
+  const dim3 grid((uint32_t)pl.main.groups), block(64 * pl.main.W);
+  if (pl.heavy == 0) {
+    if (launch(pl.set->fn, grid, block, pl.main.lds_group, s, p) != hipSuccess)
+      return HDA_E_DEVICE;
+    return hipGetLastError() == hipSuccess ? HDA_OK : HDA_E_DEVICE;
+  }
+  hipStream_t f = fork_stream();
+  if (!f) return HDA_E_DEVICE;
+  hipEvent_t e_fork = nullptr, e_join = nullptr;
+  rc = HDA_E_DEVICE;
+  ReplayParams hp = heavy_params(d, pl);
+  if (hipEventCreateWithFlags(&e_fork, hipEventDisableTiming) == hipSuccess &&
+      hipEventCreateWithFlags(&e_join, hipEventDisableTiming) == hipSuccess &&
+      hipEventRecord(e_fork, s) == hipSuccess &&
+      launch((const void*)ordered_kernel, dim3((uint32_t)pl.heavy_groups), dim3(64),
+             pl.heavy_pool, s, hp) == hipSuccess &&
+      hipStreamWaitEvent(f, e_fork, 0) == hipSuccess &&
+      launch(pl.set->fn, grid, block, pl.main.lds_group, f, p) == hipSuccess &&
+      hipEventRecord(e_join, f) == hipSuccess && hipStreamWaitEvent(s, e_join, 0) == hipSuccess)
+    rc = hipGetLastError() == hipSuccess ? HDA_OK : HDA_E_DEVICE;
+  if (e_fork) (void)hipEventDestroy(e_fork);
+  if (e_join) (void)hipEventDestroy(e_join);
+  return rc;
 }
 
 }  // namespace
@@ -420,6 +524,8 @@ int hda_replay_resolve(const hda_batch_desc* d, hda_tuning* out) {
   out->lds_free = pl.main.lds_free > 0 ? (int32_t)pl.main.lds_free : -1;
   out->lds_live = pl.main.lds_live > 0 ? (int32_t)pl.main.lds_live : -1;
   out->groups = (int32_t)pl.main.groups;
+  out->heavy_heaps = (int32_t)pl.heavy;
+  out->heavy_kib = pl.heavy > 0 ? (int32_t)(pl.heavy_pool / 1024u) : 0;
   return HDA_OK;
 }
 
@@ -648,6 +754,7 @@ extern "C" {
 int hda_replay_static(const hda_batch_desc* d, void* stream) {
   Plan pl;
   if (!desc_ok(d) || !make_plan(d, true, &pl)) return HDA_E_INVAL;
+  if (pl.heavy > 0) return HDA_E_INVAL;  // events and a second stream: use hda_replay
   if (d->n_heaps == 0) return HDA_OK;
   if (pl.bytes > kStaticScratchBytes) return HDA_E_RANGE;
   uint8_t* ws = static_scratch();
@@ -677,6 +784,7 @@ int hda_replay_capture(const hda_batch_desc* d, hda_graph** out) {
   if (!out || !desc_ok(d) || !make_plan(d, true, &pl) || d->n_heaps == 0) return HDA_E_INVAL;
   if (!d->workspace || d->workspace_bytes < pl.bytes) return HDA_E_RANGE;
   if (!set_lds_attrs(pl)) return HDA_E_DEVICE;
+  if (pl.heavy > 0 && !fork_stream()) return HDA_E_DEVICE;
   hipStream_t cs = nullptr;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return HDA_E_DEVICE;
   hda_graph* g = new hda_graph;

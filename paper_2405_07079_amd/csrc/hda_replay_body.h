@@ -7,6 +7,7 @@
 #include "hda_bitmap.h"
 #include "hda_core.h"
 #include "hda_lean.h"
+#include "hda_ordered.h"
 
 namespace hda {
 
@@ -37,6 +38,14 @@ struct ReplayParams {
   uint32_t waves_per_group;
   uint32_t lds_wave_bytes;
   int use_queue;         // 1: pull heaps from the queue; 0: wave w takes heap w
+  int64_t list_lo;       // queue mode: this launch takes list positions
+  int64_t list_hi;       //   [list_lo, min(list_hi, *count))
+  // ordered core (hda_ordered.h): per-wave LDS pool bytes, the part of it
+  // meant for chunk slots, and the device slot of each wave
+  uint32_t ord_pool_bytes;
+  uint32_t ord_slot_bytes;
+  uint8_t* ord_dev;
+  uint64_t ord_dev_stride;
 };
 
 // Validate heap parameters; on success fill the uniform heap registers.
@@ -95,7 +104,7 @@ __device__ __forceinline__ uint32_t run_block(Core& w, uint32_t n, uint32_t w0, 
 // request not run: `to`, or the request that found the lean core's tiers too
 // small (it changed nothing, and the results before it are stored).
 template <int ALGO, typename Core>
-__device__ int64_t run_requests(const ReplayParams& p, Core& w, int64_t from, int64_t to,
+__device__ __forceinline__ int64_t run_requests(const ReplayParams& p, Core& w, int64_t from, int64_t to,
                                 uint32_t shift, int64_t arena, int32_t& st) {
   const uint32_t lane = lane_id();
   const uint64_t gm = (1ull << shift) - 1ull;
@@ -143,7 +152,7 @@ __device__ __forceinline__ void finish_heap(const ReplayParams& p, Core& w, int6
 }
 
 template <int ALGO, int RF, int RL>
-__device__ void replay_heap(const ReplayParams& p, const Cold& c, const HeapRegs& regs,
+__device__ __forceinline__ void replay_heap(const ReplayParams& p, const Cold& c, const HeapRegs& regs,
                             int64_t heap) {
   WaveHeap<ALGO, RF, RL> w(c, regs, p.cap_free, p.cap_live);
   w.init();
@@ -225,6 +234,36 @@ __device__ void replay_any_heap(const ReplayParams& p, const Cold& c, int64_t he
     case kBestFit: replay_heap<kBestFit, RF, RL>(p, c, h, heap); break;
     case kSegFit: replay_heap<kSegFit, RF, RL>(p, c, h, heap); break;
     case kTlsf: replay_heap<kTlsf, RF, RL>(p, c, h, heap); break;
+    default: reject_heap(p, heap); break;  // the bitmask allocator has its own kernel
+  }
+}
+
+// Ordered core (hda_ordered.h) for one heap: tables in the wave's LDS pool
+// and, past it, in its device slot.
+template <int ALGO>
+__device__ __forceinline__ void ord_replay_heap(const ReplayParams& p, HDA_LDS uint8_t* pool,
+                                HDA_GLOBAL uint8_t* dev, const HeapRegs& regs, int64_t heap) {
+  const OrdMem m = ord_mem(ALGO, pool, p.ord_pool_bytes, p.ord_slot_bytes, dev, p.cap_live);
+  OrdHeap<ALGO> w(m, regs, p.cap_free, p.cap_live);
+  w.init();
+  int32_t st = 0;
+  run_requests<ALGO>(p, w, p.req_off[heap], p.req_off[heap + 1], regs.shift, regs.arena, st);
+  finish_heap(p, w, heap, st);
+}
+
+__device__ __forceinline__ void ord_any_heap(const ReplayParams& p, HDA_LDS uint8_t* pool,
+                                             HDA_GLOBAL uint8_t* dev, int64_t heap) {
+  HeapRegs h;
+  if (!heap_params(p, heap, h)) {
+    reject_heap(p, heap);
+    return;
+  }
+  switch (h.algo) {
+    case kFirstFit: ord_replay_heap<kFirstFit>(p, pool, dev, h, heap); break;
+    case kNextFit: ord_replay_heap<kNextFit>(p, pool, dev, h, heap); break;
+    case kBestFit: ord_replay_heap<kBestFit>(p, pool, dev, h, heap); break;
+    case kSegFit: ord_replay_heap<kSegFit>(p, pool, dev, h, heap); break;
+    case kTlsf: ord_replay_heap<kTlsf>(p, pool, dev, h, heap); break;
     default: reject_heap(p, heap); break;  // the bitmask allocator has its own kernel
   }
 }

@@ -33,10 +33,12 @@ class HdaError(RuntimeError):
 class hda_tuning(ctypes.Structure):
     _fields_ = [("heaps_per_group", ctypes.c_int32), ("reg_free", ctypes.c_int32),
                 ("reg_live", ctypes.c_int32), ("lds_free", ctypes.c_int32),
-                ("lds_live", ctypes.c_int32), ("groups", ctypes.c_int32)]
+                ("lds_live", ctypes.c_int32), ("groups", ctypes.c_int32),
+                ("heavy_heaps", ctypes.c_int32), ("heavy_kib", ctypes.c_int32)]
 
 
-TUNING_FIELDS = ("heaps_per_group", "reg_free", "reg_live", "lds_free", "lds_live", "groups")
+TUNING_FIELDS = ("heaps_per_group", "reg_free", "reg_live", "lds_free", "lds_live", "groups",
+                 "heavy_heaps", "heavy_kib")
 
 
 def tuning(**kw) -> tuple:

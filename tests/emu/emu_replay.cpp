@@ -31,6 +31,7 @@ struct LaneJob {
   uint64_t* nodes;
   Ent* live;
   uint64_t max_granules;
+  uint8_t* ord_dev;      // ordered core: the wave's device slot
 };
 LaneJob g_job;
 
@@ -52,6 +53,7 @@ void lane_main() {
     case 2: replay_any_heap<4, 8>(*g_job.p, *g_job.c, g_job.heap); break;
     case 3: lean_any<1>(*g_job.p, *g_job.lds, *g_job.c, g_job.heap); break;
     case 4: lean_any<4>(*g_job.p, *g_job.lds, *g_job.c, g_job.heap); break;
+    case 6: ord_any_heap(*g_job.p, g_job.lds->base, g_job.ord_dev, g_job.heap); break;
     default:
       bitmap_one_heap(*g_job.p, g_job.bits, g_job.nodes, g_job.live, g_job.max_granules,
                       g_job.heap);
@@ -69,7 +71,7 @@ void lane_main() {
   }
 }
 
-const int kShapeRF[] = {0, 1, 4, 0, 0, 0}, kShapeRL[] = {0, 2, 8, 0, 0, 0};
+const int kShapeRF[] = {0, 1, 4, 0, 0, 0, 0}, kShapeRL[] = {0, 2, 8, 0, 0, 0, 0};
 
 // The bitmask allocator's node summaries recomputed granule by granule from
 // the flags: bottom run | top run << 16 | longest run << 32 per 4,096
@@ -113,7 +115,9 @@ void run_wave(EmuWave& w, std::vector<std::vector<uint8_t>>& stacks) {
 // chunks in registers; lean core with 3 = one, 4 = four free chunks in
 // registers, where a heap that outgrows its tiers moves to the general core
 // on the same "LDS" plus spill tables (overflowed[h] = 1); 5 = the bitmask
-// allocator (flags for the heap's own granules, cap_live live entries).
+// allocator (flags for the heap's own granules, cap_live live entries); 6 =
+// the ordered core with a pool of 8 KiB + kf * 16 + kl * 8 bytes, kf * 16 of
+// them meant for chunk slots.
 // kf/kl: entries in "LDS"; cap_free/cap_live: capacities.
 extern "C" int emu_replay(int64_t H, const int64_t* arena, const int64_t* align,
                           const int32_t* algo, const int64_t* req_off, const int64_t* req,
@@ -127,6 +131,31 @@ extern "C" int emu_replay(int64_t H, const int64_t* arena, const int64_t* align,
   p.res = res; p.state = state; p.state_off = state_off; p.state_len = state_len;
   p.status = status;
   const bool lean = shape == 3 || shape == 4;
+  if (shape == 6) {
+    // ordered core: its own pool and device slot, poisoned per heap
+    p.cap_free = cap_free; p.cap_live = cap_live;
+    p.ord_pool_bytes = 8192u + kf * 16u + kl * 8u;
+    p.ord_slot_bytes = kf * 16u;
+    std::vector<uint8_t> opool(size_t(p.ord_pool_bytes) + 16);
+    std::vector<uint8_t> odev(size_t(ord_dev_bytes(cap_live)) + 16);
+    const size_t stack_bytes = 256 * 1024;
+    std::vector<std::vector<uint8_t>> stacks(64, std::vector<uint8_t>(stack_bytes));
+    EmuWave w;
+    emu_wave = &w;
+    for (int64_t h = 0; h < H; ++h) {
+      std::memset(opool.data(), 0xA5, opool.size());
+      std::memset(odev.data(), 0xA5, odev.size());
+      LeanLds ll;
+      ll.base = opool.data();
+      ll.bytes = p.ord_pool_bytes;
+      g_job = LaneJob{&p, nullptr, &ll, h, shape, 0};
+      g_job.ord_dev = odev.data();
+      run_wave(w, stacks);
+      if (syncs) syncs[h] = w.syncs;
+    }
+    emu_wave = nullptr;
+    return 0;
+  }
   // lean core: an LDS pool with room for kf 16-byte free and kl live entries;
   // the general core it may move to has no LDS part
   const uint32_t pool = kf * 16u + kl * 8u;

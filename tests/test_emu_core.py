@@ -266,3 +266,56 @@ def test_bitmap_live_capacity():
     ores, _ = oracle.replay_heap(5, int(b.arena[0]), int(b.align[0]), b.req)
     k = int(np.nonzero(res == -4)[0][0])
     assert np.array_equal(res[:k], ores[:k])
+
+
+# ---- the ordered core (free blocks in address-ordered chunks, directory in
+# VGPRs; shape 6: a pool of 8 KiB + kf * 16 + kl * 8 bytes, kf * 16 of them
+# for chunk slots, the rest of each table in the device slot) ----
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_ordered_single_heap_64KiB(algo):
+    b = W.single_heap(n=3000).with_algo(algo)
+    res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=4096, cl=8192, shape=6)
+    check(b, res, states, status)
+
+
+@pytest.mark.parametrize("algo", ALGOS)
+def test_ordered_many_free_blocks(algo):
+    """Hundreds of free blocks of small sizes: chunks split at 64 entries,
+    merge or share entries below 32, and most of them sit past the pool's
+    slots in the device slot."""
+    b = W.uniform_batch(seed=7, heaps=1, arena=1 << 24, align=16, n=9000, p_alloc=0.56,
+                        lo=16, hi=160, algo=algo, name="tiny_blocks")
+    res, states, status, _ = emu.replay(b, kf=256, kl=256, cf=4096, cl=16384, shape=6)
+    check(b, res, states, status)
+    assert int(states[0][0]) > 64, "the free blocks should span several chunks"
+
+
+def test_ordered_random_small_heaps_and_partial_frees():
+    rng = np.random.default_rng(13)
+    parts = []
+    for h in range(30):
+        gran = int(rng.integers(1, 400))
+        parts.append(W.random_tiny(int(rng.integers(1 << 30)), int(rng.integers(0, 400)),
+                                   gran, align=int(1 << rng.integers(0, 12)),
+                                   algo=int(rng.integers(0, 5)),
+                                   max_granules=max(1, gran // int(rng.integers(1, 8))),
+                                   p_partial=float(rng.uniform(0.0, 1.0))))
+    b = W.concat(parts)
+    res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=512, cl=512, shape=6)
+    check(b, res, states, status)
+
+
+def test_ordered_max_arena_edges_and_capacity():
+    b = W.max_arena_batch()
+    res, states, status, _ = emu.replay(b, kf=64, kl=64, cf=64, cl=192, shape=6)
+    check(b, res, states, status)
+    # at its capacities the ordered core refuses the same requests as the
+    # lean core and ends in the same states
+    b = W.concat([W.uniform_batch(seed=9, heaps=1, n=2500, algo=a) for a in ALGOS], "cap")
+    r6, s6, st6, _ = emu.replay(b, kf=64, kl=64, cf=64, cl=192, shape=6)
+    r3, s3, st3, _ = emu.replay(b, kf=64, kl=64, cf=64, cl=192, shape=3)
+    assert (st3 == -4).all()
+    assert np.array_equal(r6, r3) and np.array_equal(st6, st3)
+    for h in range(b.heaps):
+        assert np.array_equal(s6[h], s3[h])
