@@ -6,44 +6,53 @@
 // the hybrid array list of App. A, whose traversal costs O(n/m + m) on one
 // CPU thread.  Here a directory held in D VGPRs replaces the walk over the
 // chunk list: lane l of directory register v describes chunk 64 v + l in
-// address order (its storage slot, its number of entries, its first key and,
-// for first and next fit, the largest block in it).  Finding the chunk that
-// holds an address, or the first chunk holding a block of at least s
-// granules, is one ballot per directory register; finding the entry inside
-// it is one chunk load and one ballot.  A full chunk splits into 33 + 32
-// entries; a chunk that drops below 32 entries merges with a neighbour or
-// takes entries from it.  So while there are two or more chunks each holds at
-// least 32 entries, and the directory's 64 D chunks always hold 2,048 D free
-// blocks.
+// order (its storage slot, its number of entries, its first key and, for
+// first and next fit, the largest block in it).  Finding the chunk that
+// holds a key, or the first chunk holding a block of at least s granules,
+// is one ballot per directory register; finding the entry inside it is one
+// chunk load and one ballot.  A full chunk splits into 33 + 32 entries; a
+// chunk that drops below 32 entries merges with a neighbour or takes entries
+// from it.  So while there are two or more chunks each holds at least 32
+// entries, and the directory's 64 D chunks always hold 2,048 D free blocks.
+//
+// A free block's entry is keyed by its END granule address.  Free blocks do
+// not overlap, so this is also address order, and Alg. 1 / Alg. 4 cut an
+// allocation from the low end of a block: the remainder keeps its end, so
+// splitting a block rewrites its size (or its record) and never its place.
+// The block ending at a freed block's start is an exact key match; the one
+// after it is the next entry.
 //
 // Per algorithm:
-//  * first fit (Sec. II-A): the first chunk whose largest block fits, then
-//    the first fitting entry in it.
-//  * next fit (Sec. II-A, Sec. IV): the block holding the rover or the next
-//    one is located like an address; the search runs on from there through
-//    the directory and wraps once.
-//  * best fit (Alg. 3): a second sorted chunk table holds the keys
-//    (size, address); the smallest key at or above (s, 0) is the best fit.
-//  * segregated fit (Alg. 4-5) and TLSF (Sec. V-B): each free entry carries
-//    the class-list links of Alg. 4-5 (next and previous block, by address,
-//    NIL = kNone), the list heads sit in a VGPR (segregated fit: lane k heads
-//    class k) or in LDS (TLSF's 2,048 classes), and the availability bitmaps
-//    are a scalar (segregated fit; TLSF's first level) and a VGPR (TLSF's
-//    second level: lane fl holds the 32 sub-class bits of level fl).  The
-//    paper's address-keyed hash lookup ht[addr] becomes a lookup in the
-//    address-ordered table; the block ending at a freed block and the one
-//    after it are its neighbours in that order (no prev_adj field needed).
+//  * first fit (Sec. II-A): entries (end, size); the first chunk whose
+//    largest block fits, then the first fitting entry in it.
+//  * next fit (Sec. II-A, Sec. IV): the first block ending past the rover
+//    is located like a key; the search runs on from there through the
+//    directory and wraps once.
+//  * best fit (Alg. 3): entries (end, size) and a second sorted chunk table
+//    of keys (size, end) -- among blocks of one size the lowest end is the
+//    lowest address; the smallest key at or above (s, 0) is the best fit.
+//  * segregated fit (Alg. 4-5) and TLSF (Sec. V-B): entries (end, record).
+//    A record holds the block's address and size and its class-list links
+//    (next and previous record, NIL = kNone), as Alg. 4-5 keep them; record
+//    numbers never change while a block is free, so unlinking and pushing
+//    are stores with no search.  Free record numbers are bits of a VGPR
+//    pair (lane l: records 64 l .. 64 l + 63).  List heads are in a VGPR
+//    (segregated fit: lane k heads class k) or in LDS (TLSF's 2,048
+//    classes); the bitmaps are a scalar (segregated fit; TLSF's first level)
+//    and a VGPR (TLSF's second level: lane fl holds level fl's 32 bits).
+//    The paper's address-keyed hash lookup ht[addr] becomes the key lookup
+//    in the table.
 //
 // Results equal those of the other cores and the oracle: selection,
 // splitting, merging and the class lists follow the same definitions.
 //
-// Storage: chunk slots and live entries below the LDS counts given at
-// construction are in the wave's LDS pool, the rest in its device-memory
+// Storage: chunk slots, records and live entries below the LDS counts given
+// at construction are in the wave's LDS pool, the rest in its device-memory
 // slot.  Every memory access is preceded by wave_sync() (a no-op on the GPU;
 // the CPU wave emulation switches lanes there).  As in the other cores,
 // values that feed a cross-lane operation are never produced under a
-// lane-dependent branch, and every entry write is done by all lanes with the
-// same value.
+// lane-dependent branch, and every single-entry write is done by all lanes
+// with the same value.
 #pragma once
 #include <stdint.h>
 
@@ -107,37 +116,38 @@ __device__ __forceinline__ void dir_erase(uint32_t (&v)[D], uint32_t i, uint32_t
   }
 }
 
-// One table of sorted chunks.  REC: 16-byte entries (address, size, next,
-// prev) instead of 8-byte ones (address, size).  KEY64: sorted by (size,
-// address) instead of by address.  MAXS: the directory keeps each chunk's
-// largest size.
-template <bool REC, bool KEY64, bool MAXS, int D>
+// One table of sorted chunks of 8-byte entries (key, value): the key is a
+// block's end granule, the value its size or its record.  KEY64: sorted by
+// (value, key) instead (best fit's (size, end) keys).  MAXS: the directory
+// keeps each chunk's largest value (first and next fit: the largest size).
+template <bool KEY64, bool MAXS, int D>
 struct Hal {
-  static constexpr uint32_t NC = 64u * D;         // chunk slots
-  static constexpr uint32_t EB = REC ? 16u : 8u;  // bytes per entry
-  static constexpr uint32_t CB = 64u * EB;        // bytes per chunk
+  static constexpr uint32_t NC = 64u * D;  // chunk slots
+  static constexpr uint32_t CB = 64u * 8u; // bytes per chunk
 
   // this lane's entry of a loaded chunk; positions past the chunk's count
-  // hold the sentinel (address kNone, size 0, or size kNone when sorted by
-  // size), which sorts after every real entry and fits no request
+  // hold the sentinel (key kNone, value 0, or value kNone when sorted by
+  // value), which sorts after every real entry and fits no request
   struct Row {
-    uint32_t a, s, nx, pv;
+    uint32_t a, s;
   };
 
+  static constexpr int ND = D;
   HDA_LDS uint8_t* lb;     // slots [0, nl) in LDS
   HDA_GLOBAL uint8_t* gb;  // slot i >= nl at gb + i * CB in device memory
-  uint32_t nl;
-  uint32_t dsl[D], dct[D], dk0[D], dk1[D], dmx[D];  // slot, count, first key, max size
+  uint32_t nl, nl_req;     // LDS slots (nl_req as asked for, nl within NC)
+  uint32_t dsl[D], dct[D], dk0[D], dk1[D], dmx[D];  // slot, count, first key, max value
   uint64_t used[D];                                 // slots in use
   uint32_t nc;                                      // chunks
 
   static constexpr uint32_t kSentS = KEY64 ? kNone : 0u;
 
-  __device__ __forceinline__ static Row sentinel() { return Row{kNone, kSentS, kNone, kNone}; }
+  __device__ __forceinline__ static Row sentinel() { return Row{kNone, kSentS}; }
 
   __device__ __forceinline__ void init(HDA_LDS uint8_t* l, HDA_GLOBAL uint8_t* g, uint32_t n_lds) {
     lb = l;
     gb = g;
+    nl_req = n_lds;
     nl = n_lds < NC ? n_lds : NC;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -147,67 +157,44 @@ struct Hal {
     nc = 0;
   }
 
-  // ---- chunk memory ----
+  // ---- chunk memory (slot ids are below NC; the clamps keep every access
+  // inside the table whatever happens) ----
   __device__ __forceinline__ Row load(uint32_t sl) const {
     wave_sync();
-    sl = sl < NC ? sl : NC - 1u;  // (slot ids are below NC; kept in the table)
+    sl = sl < NC ? sl : NC - 1u;
     const uint32_t lane = lane_id();
-    Row r;
-    if constexpr (REC) {
-      u32x4 v;
-      if (sl < nl) v = *(const HDA_LDS u32x4*)(lb + sl * CB + lane * 16u);
-      else v = *(const HDA_GLOBAL u32x4*)(gb + (uint64_t)sl * CB + lane * 16u);
-      r.a = v[0]; r.s = v[1]; r.nx = v[2]; r.pv = v[3];
-    } else {
-      u32x2 v;
-      if (sl < nl) v = *(const HDA_LDS u32x2*)(lb + sl * CB + lane * 8u);
-      else v = *(const HDA_GLOBAL u32x2*)(gb + (uint64_t)sl * CB + lane * 8u);
-      r.a = v[0]; r.s = v[1]; r.nx = kNone; r.pv = kNone;
-    }
-    return r;
+    u32x2 v;
+    if (sl < nl) v = *(const HDA_LDS u32x2*)(lb + sl * CB + lane * 8u);
+    else v = *(const HDA_GLOBAL u32x2*)(gb + (uint64_t)sl * CB + lane * 8u);
+    return Row{v[0], v[1]};
   }
   __device__ __forceinline__ void store(uint32_t sl, const Row& r) const {
     wave_sync();
-    sl = sl < NC ? sl : NC - 1u;  // (slot ids are below NC; kept in the table)
+    sl = sl < NC ? sl : NC - 1u;
     const uint32_t lane = lane_id();
-    if constexpr (REC) {
-      u32x4 v;
-      v[0] = r.a; v[1] = r.s; v[2] = r.nx; v[3] = r.pv;
-      if (sl < nl) *(HDA_LDS u32x4*)(lb + sl * CB + lane * 16u) = v;
-      else *(HDA_GLOBAL u32x4*)(gb + (uint64_t)sl * CB + lane * 16u) = v;
-    } else {
-      u32x2 v;
-      v[0] = r.a; v[1] = r.s;
-      if (sl < nl) *(HDA_LDS u32x2*)(lb + sl * CB + lane * 8u) = v;
-      else *(HDA_GLOBAL u32x2*)(gb + (uint64_t)sl * CB + lane * 8u) = v;
-    }
+    u32x2 v;
+    v[0] = r.a; v[1] = r.s;
+    if (sl < nl) *(HDA_LDS u32x2*)(lb + sl * CB + lane * 8u) = v;
+    else *(HDA_GLOBAL u32x2*)(gb + (uint64_t)sl * CB + lane * 8u) = v;
   }
-  // one 32-bit field (0 address, 1 size, 2 next, 3 prev) of entry p, written
-  // by every lane with the same value
+  // field f (0 key, 1 value) of entry p, written by every lane
   __device__ __forceinline__ void store_field(uint32_t sl, uint32_t p, uint32_t f,
                                               uint32_t x) const {
     wave_sync();
     sl = sl < NC ? sl : NC - 1u;
-    const uint32_t off = (p & 63u) * EB + (f & 3u) * 4u;
+    const uint32_t off = (p & 63u) * 8u + (f & 1u) * 4u;
     if (sl < nl) *(HDA_LDS uint32_t*)(lb + sl * CB + off) = x;
     else *(HDA_GLOBAL uint32_t*)(gb + (uint64_t)sl * CB + off) = x;
   }
-  __device__ __forceinline__ void store_entry(uint32_t sl, uint32_t p, uint32_t a, uint32_t s,
-                                              uint32_t nx, uint32_t pv) const {
+  __device__ __forceinline__ void store_entry(uint32_t sl, uint32_t p, uint32_t a,
+                                              uint32_t s) const {
     wave_sync();
-    p &= 63u;  // (positions are below 64; the mask keeps every store in its chunk)
     sl = sl < NC ? sl : NC - 1u;
-    if constexpr (REC) {
-      u32x4 v;
-      v[0] = a; v[1] = s; v[2] = nx; v[3] = pv;
-      if (sl < nl) *(HDA_LDS u32x4*)(lb + sl * CB + p * 16u) = v;
-      else *(HDA_GLOBAL u32x4*)(gb + (uint64_t)sl * CB + p * 16u) = v;
-    } else {
-      u32x2 v;
-      v[0] = a; v[1] = s;
-      if (sl < nl) *(HDA_LDS u32x2*)(lb + sl * CB + p * 8u) = v;
-      else *(HDA_GLOBAL u32x2*)(gb + (uint64_t)sl * CB + p * 8u) = v;
-    }
+    u32x2 v;
+    v[0] = a; v[1] = s;
+    const uint32_t off = (p & 63u) * 8u;
+    if (sl < nl) *(HDA_LDS u32x2*)(lb + sl * CB + off) = v;
+    else *(HDA_GLOBAL u32x2*)(gb + (uint64_t)sl * CB + off) = v;
   }
 
   // ---- keys ----
@@ -233,7 +220,7 @@ struct Hal {
   __device__ __forceinline__ uint32_t slot(uint32_t ci) const { return dir_get(dsl, ci); }
   __device__ __forceinline__ uint32_t count(uint32_t ci) const { return dir_get(dct, ci); }
 
-  // Directory entry of chunk ci from its loaded row (n entries).
+  // Directory entry of chunk ci from its row (n entries).
   __device__ __forceinline__ void describe(uint32_t ci, const Row& r, uint32_t n) {
     dir_put(dct, ci, n);
     dir_put(dk0, ci, rdlane(r.a, 0));
@@ -263,36 +250,37 @@ struct Hal {
   }
 
   // A table holding one entry.
-  __device__ __forceinline__ void start(uint32_t a, uint32_t s, uint32_t nx, uint32_t pv) {
+  __device__ __forceinline__ void start(uint32_t a, uint32_t s) {
     const uint32_t sl = take_slot();
     Row r = sentinel();
     const bool me = lane_id() == 0u;
-    r.a = me ? a : r.a; r.s = me ? s : r.s; r.nx = me ? nx : r.nx; r.pv = me ? pv : r.pv;
+    r.a = me ? a : r.a;
+    r.s = me ? s : r.s;
     store(sl, r);
     nc = 1;
     dir_put(dsl, 0u, sl);
     describe(0u, r, 1u);
   }
 
-  // Row shifted: lane l receives lane src(l) of r (or the sentinel when the
-  // source is out of range).
+  // Row shifted: lane l receives lane src(l) of r (the sentinel when !ok).
   __device__ __forceinline__ static Row pull(const Row& r, uint32_t src, bool ok) {
-    Row o;
     const uint32_t s = src & 63u;
-    o.a = shfl(r.a, s); o.s = shfl(r.s, s);
-    if (REC) { o.nx = shfl(r.nx, s); o.pv = shfl(r.pv, s); } else { o.nx = o.pv = kNone; }
-    const Row z = sentinel();
-    o.a = ok ? o.a : z.a; o.s = ok ? o.s : z.s; o.nx = ok ? o.nx : z.nx; o.pv = ok ? o.pv : z.pv;
+    Row o{shfl(r.a, s), shfl(r.s, s)};
+    o.a = ok ? o.a : kNone;
+    o.s = ok ? o.s : kSentS;
     return o;
   }
   __device__ __forceinline__ static Row pick(bool c, const Row& x, const Row& y) {
-    Row o;
-    o.a = c ? x.a : y.a; o.s = c ? x.s : y.s; o.nx = c ? x.nx : y.nx; o.pv = c ? x.pv : y.pv;
-    return o;
+    return Row{c ? x.a : y.a, c ? x.s : y.s};
+  }
+  // r with lane p's entry replaced
+  __device__ __forceinline__ static Row with(const Row& r, uint32_t p, uint32_t a, uint32_t s) {
+    const bool me = lane_id() == p;
+    return Row{me ? a : r.a, me ? s : r.s};
   }
 
   // Insert entry e at position p (0 <= p <= count) of chunk ci, whose row r
-  // has just been loaded.  The caller guarantees order and capacity.
+  // is current.  The caller guarantees order and capacity.
   __device__ __forceinline__ void insert_at(uint32_t ci, uint32_t p, const Row& r, const Row& e) {
     const uint32_t lane = lane_id();
     const uint32_t n = count(ci), sl = slot(ci);
@@ -325,8 +313,8 @@ struct Hal {
     ++nc;
   }
 
-  // Remove the entry at position p of chunk ci (row r just loaded), then
-  // keep every chunk at 32 entries or more while there are two or more.
+  // Remove the entry at position p of chunk ci (row r current), then keep
+  // every chunk at 32 entries or more while there are two or more.
   __device__ __forceinline__ void erase_at(uint32_t ci, uint32_t p, const Row& r) {
     const uint32_t lane = lane_id();
     const uint32_t n = count(ci) - 1u, sl = slot(ci);
@@ -375,9 +363,9 @@ struct Hal {
     describe(hi, m1, b);
   }
 
-  // The chunk holding key (k1, k0) or the last chunk whose first key is
-  // below it: ci (kNone if every chunk starts above it), its row, and p =
-  // the position of the last entry <= the key (kNone if none).
+  // The last chunk whose first key is <= (k1, k0): ci (kNone if every chunk
+  // starts above it), its row, and p = the position of the last entry <= the
+  // key in it.
   __device__ __forceinline__ void locate(uint32_t k1, uint32_t k0, uint32_t& ci, Row& r,
                                          uint32_t& p) const {
     const uint32_t c = count_first(k1, k0, false);
@@ -397,13 +385,12 @@ struct Hal {
     const uint32_t n = count(ci);
     p = (uint32_t)__builtin_popcountll(ballot(lane_id() < n && row_lt(r, k1, k0)));
   }
+  // (value, key) tables: insert and remove one key
   __device__ __forceinline__ void insert_key(uint32_t a, uint32_t s) {
     uint32_t ci, p;
     Row r;
     insert_pos(s, a, ci, r, p);
-    Row e = sentinel();
-    e.a = a; e.s = s;
-    insert_at(ci, p, r, e);
+    insert_at(ci, p, r, Row{a, s});
   }
   __device__ __forceinline__ void erase_key(uint32_t a, uint32_t s) {
     uint32_t ci, p;
@@ -411,8 +398,8 @@ struct Hal {
     locate(s, a, ci, r, p);
     erase_at(ci, p, r);
   }
-  // first chunk at or after `from` whose largest block has >= sg granules
-  // (MAXS tables), or kNone
+  // first chunk at or after `from` whose largest value is >= sg (MAXS
+  // tables), or kNone
   __device__ __forceinline__ uint32_t first_fit_chunk(uint32_t sg, uint32_t from) const {
     uint32_t c = kNone;
 #pragma unroll
@@ -425,45 +412,42 @@ struct Hal {
   }
 };
 
-// Where one heap's tables live.  Table slots and live entries below the LDS
-// counts are in the wave's LDS pool; the others are in its device slot.
+// Where one heap's tables live.  Table slots, records and live entries below
+// the LDS counts are in the wave's LDS pool; the others are in its device
+// slot.
 struct OrdMem {
   HDA_LDS uint8_t* ta_l;
   HDA_GLOBAL uint8_t* ta_g;
   uint32_t ta_n;
-  HDA_LDS uint8_t* tb_l;
+  HDA_LDS uint8_t* tb_l;     // best fit's key table
   HDA_GLOBAL uint8_t* tb_g;
   uint32_t tb_n;
+  HDA_LDS u32x4* rec_l;      // segregated fit / TLSF records
+  HDA_GLOBAL u32x4* rec_g;
+  uint32_t rec_n;
   HDA_LDS Ent* ll;
   HDA_GLOBAL Ent* gl;
   uint32_t ll_n;
-  HDA_LDS uint32_t* heads;  // TLSF list heads (2,048 words, LDS)
+  HDA_LDS uint32_t* heads;   // TLSF list heads (2,048 words, LDS)
 };
 
-constexpr int kOrdDir = 2;                          // directory registers
+constexpr int kOrdDir = 2;                          // directory registers at most
 constexpr uint32_t kOrdSlots = 64u * kOrdDir;      // chunk slots per table
 constexpr uint32_t kOrdMaxFree = 32u * kOrdSlots;  // free blocks always held
 constexpr uint32_t kOrdTlsfHeadBytes = kTlsfClasses * 4u;
-
-// Bytes of chunk slots of the address table (a) and of best fit's key
-// table (b) for an algorithm.
-__host__ __device__ constexpr uint32_t ord_chunk_a(int algo) {
-  return 64u * (seg_like(algo) ? 16u : 8u);
-}
-__host__ __device__ constexpr uint32_t ord_chunk_b(int algo) {
-  return algo == kBestFit ? 64u * 8u : 0u;
-}
-// Device bytes per wave: every slot of both tables and every live entry
-// (slots and entries held in LDS keep an unused place here).
-// The address table of segregated fit (1 KiB a chunk) is the largest; best
-// fit's two tables of 512 B chunks take as much together.
-constexpr uint64_t kOrdTableBytes = (uint64_t)kOrdSlots * (64u * 16u);
+constexpr uint32_t kOrdChunkBytes = 64u * 8u;
+// Device bytes per wave: every chunk slot of the table (64 KiB), then best
+// fit's key table or the records (64 KiB either), then the live table.
+// Slots, records and entries held in LDS keep an unused place here.
+constexpr uint64_t kOrdTableBytes = (uint64_t)kOrdSlots * kOrdChunkBytes;
+constexpr uint64_t kOrdSecondBytes = (uint64_t)kOrdMaxFree * 16u;
+static_assert(kOrdSecondBytes == kOrdTableBytes, "key table and records share one area");
 __host__ __device__ constexpr uint64_t ord_dev_bytes(uint32_t cap_live) {
-  return kOrdTableBytes + (uint64_t)cap_live * 8u;
+  return kOrdTableBytes + kOrdSecondBytes + (uint64_t)cap_live * 8u;
 }
 
-// Split a wave's pool (`pool` bytes, of which `slot_bytes` are meant for
-// chunk slots) and its device slot for an algorithm.
+// Split a wave's pool (`pool_bytes`, of which `slot_bytes` are meant for the
+// tables and records) and its device slot for an algorithm.
 __device__ __forceinline__ OrdMem ord_mem(int algo, HDA_LDS uint8_t* pool, uint32_t pool_bytes,
                                           uint32_t slot_bytes, HDA_GLOBAL uint8_t* dev,
                                           uint32_t cap_live) {
@@ -471,34 +455,45 @@ __device__ __forceinline__ OrdMem ord_mem(int algo, HDA_LDS uint8_t* pool, uint3
   uint32_t off = 0;
   m.heads = (HDA_LDS uint32_t*)pool;
   if (algo == kTlsf) off += kOrdTlsfHeadBytes;
-  const uint32_t ca = ord_chunk_a(algo), cb = ord_chunk_b(algo);
-  uint32_t na = slot_bytes / (ca + cb);
-  na = na < kOrdSlots ? na : kOrdSlots;
   const uint32_t room = pool_bytes > off ? pool_bytes - off : 0u;
-  na = na * (ca + cb) <= room ? na : room / (ca + cb);
+  const uint32_t area = slot_bytes < room ? slot_bytes : room;
+  // first and next fit: every slot of the table; best fit: half for each of
+  // its two tables; segregated fit, TLSF: half for table slots, half for
+  // records
+  const bool two = algo == kBestFit || seg_like(algo);
+  uint32_t na = (two ? area / 2u : area) / kOrdChunkBytes;
+  na = na < kOrdSlots ? na : kOrdSlots;
   m.ta_l = pool + off;
   m.ta_n = na;
-  off += na * ca;
+  off += na * kOrdChunkBytes;
   m.tb_l = pool + off;
-  m.tb_n = cb ? na : 0u;
-  off += cb ? na * cb : 0u;
+  m.tb_n = algo == kBestFit ? na : 0u;
+  off += algo == kBestFit ? na * kOrdChunkBytes : 0u;
+  uint32_t nr = seg_like(algo) ? (area / 2u) / 16u : 0u;
+  nr = nr < kOrdMaxFree ? nr : kOrdMaxFree;
+  m.rec_l = (HDA_LDS u32x4*)(pool + off);
+  m.rec_n = nr;
+  off += nr * 16u;
   m.ta_g = dev;
-  m.tb_g = dev + (uint64_t)kOrdSlots * ca;
+  m.tb_g = dev + kOrdTableBytes;
+  m.rec_g = (HDA_GLOBAL u32x4*)(dev + kOrdTableBytes);
   m.ll = (HDA_LDS Ent*)(pool + off);
   const uint32_t nl = pool_bytes > off ? (pool_bytes - off) / 8u : 0u;
   m.ll_n = nl < cap_live ? nl : cap_live;
-  m.gl = (HDA_GLOBAL Ent*)(dev + kOrdTableBytes);
+  m.gl = (HDA_GLOBAL Ent*)(dev + kOrdTableBytes + kOrdSecondBytes);
   return m;
 }
 
-template <int ALGO>
+// D: directory registers.  A heap starts with one; a request that finds a
+// table at 64 chunks returns kOverflow before changing anything, and the
+// heap continues with two (take()), which hold every table this core allows.
+template <int ALGO, int D>
 struct OrdHeap {
-  static constexpr int D = kOrdDir;
   static constexpr bool kSeg = ALGO == kSegFit || ALGO == kTlsf;
   static constexpr bool kKeys = ALGO == kBestFit;
   static constexpr bool kMax = ALGO == kFirstFit || ALGO == kNextFit;
-  using TA = Hal<kSeg, false, kMax, D>;
-  using TB = Hal<false, true, false, D>;
+  using TA = Hal<false, kMax, D>;
+  using TB = Hal<true, false, D>;
   using Row = typename TA::Row;
 
   TA ta;
@@ -508,9 +503,10 @@ struct OrdHeap {
   uint32_t shift, ag;
   uint32_t F, L, rover;
   uint32_t capF, capL;
-  uint32_t hd;      // segregated fit: lane k = head of class k's list (kNone: empty)
-  uint64_t bm;      // segregated fit: class bitmap; TLSF: first-level bitmap
-  uint32_t slb;     // TLSF: lane fl = bitmap of the 32 sub-classes of level fl
+  uint32_t hd;          // segregated fit: lane k = head record of class k (kNone: empty)
+  uint64_t bm;          // segregated fit: class bitmap; TLSF: first-level bitmap
+  uint32_t slb;         // TLSF: lane fl = bitmap of the 32 sub-classes of level fl
+  uint32_t frl, frh;    // free records: lane l, bit b <=> record 64 l + b (low, high word)
 
   __device__ __forceinline__ OrdHeap(const OrdMem& mem, const HeapRegs& h, uint32_t cap_free,
                                      uint32_t cap_live)
@@ -518,10 +514,15 @@ struct OrdHeap {
         capF(cap_free < kOrdMaxFree ? cap_free : kOrdMaxFree), capL(cap_live) {}
 
   // ---- live table ----
+  // (every lane reads the same entry; the halves are made wave-uniform so
+  // that what is computed from them stays scalar)
   __device__ __forceinline__ Ent lget(uint32_t i) const {
+    const Ent e = lraw(i);
+    return mk_ent(uniform(ent_a(e)), uniform(ent_s(e)));
+  }
+  __device__ __forceinline__ Ent lraw(uint32_t i) const {
     wave_sync();
-    if (i < m.ll_n) return m.ll[i];
-    return m.gl[i];
+    return i < m.ll_n ? m.ll[i] : m.gl[i];
   }
   __device__ __forceinline__ void lset(uint32_t i, Ent e) const {
     wave_sync();
@@ -534,6 +535,54 @@ struct OrdHeap {
     return m.gl[i];
   }
 
+  // ---- records (segregated fit, TLSF): address, size, next, prev ----
+  struct Rec {
+    uint32_t a, s, nx, pv;
+  };
+  __device__ __forceinline__ u32x4 rec_raw(uint32_t i) const {
+    wave_sync();
+    i = i < kOrdMaxFree ? i : kOrdMaxFree - 1u;
+    u32x4 v;
+    if (i < m.rec_n) v = m.rec_l[i]; else v = m.rec_g[i];
+    return v;
+  }
+  __device__ __forceinline__ static Rec rec_of(const u32x4& v) {
+    return Rec{uniform(v[0]), uniform(v[1]), uniform(v[2]), uniform(v[3])};
+  }
+  __device__ __forceinline__ Rec rec(uint32_t i) const { return rec_of(rec_raw(i)); }
+  __device__ __forceinline__ void rec_put(uint32_t i, uint32_t a, uint32_t s, uint32_t nx,
+                                          uint32_t pv) const {
+    wave_sync();
+    i = i < kOrdMaxFree ? i : kOrdMaxFree - 1u;
+    u32x4 v;
+    v[0] = a; v[1] = s; v[2] = nx; v[3] = pv;
+    if (i < m.rec_n) m.rec_l[i] = v; else m.rec_g[i] = v;
+  }
+  // one field (2 next, 3 prev) of record i
+  __device__ __forceinline__ void rec_link(uint32_t i, uint32_t f, uint32_t x) const {
+    wave_sync();
+    i = i < kOrdMaxFree ? i : kOrdMaxFree - 1u;
+    if (i < m.rec_n) ((HDA_LDS uint32_t*)(m.rec_l + i))[f & 3u] = x;
+    else ((HDA_GLOBAL uint32_t*)(m.rec_g + i))[f & 3u] = x;
+  }
+  __device__ __forceinline__ uint32_t rec_take() {
+    const uint64_t m1 = ballot(frl != 0u || frh != 0u);
+    const uint32_t l = m1 != 0ull ? ctz64(m1) : 63u;
+    const uint32_t wl = rdlane(frl, l), wh = rdlane(frh, l);
+    const uint32_t b = wl != 0u ? (uint32_t)__builtin_ctz(wl)
+                                : 32u + (uint32_t)__builtin_ctz(wh != 0u ? wh : 1u);
+    const bool me = lane_id() == l;
+    frl = me && b < 32u ? frl & ~(1u << b) : frl;
+    frh = me && b >= 32u ? frh & ~(1u << (b - 32u)) : frh;
+    return 64u * l + b;
+  }
+  __device__ __forceinline__ void rec_give(uint32_t i) {
+    const bool me = lane_id() == (i >> 6);
+    const uint32_t b = i & 63u;
+    frl = me && b < 32u ? frl | (1u << b) : frl;
+    frh = me && b >= 32u ? frh | (1u << (b - 32u)) : frh;
+  }
+
   // ---- class lists (segregated fit, TLSF) ----
   __device__ __forceinline__ uint32_t cls(uint32_t sg) const {
     return ALGO == kTlsf ? tlsf_class(sg, shift) : floor_log2_u32(sg) + shift;
@@ -541,17 +590,17 @@ struct OrdHeap {
   __device__ __forceinline__ uint32_t head(uint32_t c) const {
     if constexpr (ALGO == kTlsf) {
       wave_sync();
-      return m.heads[c];
+      return uniform(m.heads[c]);
     } else {
       return rdlane(hd, c);
     }
   }
-  __device__ __forceinline__ void set_head(uint32_t c, uint32_t a) {
+  __device__ __forceinline__ void set_head(uint32_t c, uint32_t i) {
     if constexpr (ALGO == kTlsf) {
       wave_sync();
-      m.heads[c] = a;
+      m.heads[c] = i;
     } else {
-      hd = put_lane(hd, c, a);
+      hd = put_lane(hd, c, i);
     }
   }
   __device__ __forceinline__ void bit_set(uint32_t c) {
@@ -571,33 +620,26 @@ struct OrdHeap {
       bm &= ~(1ull << c);
     }
   }
-  // field f (2 next, 3 prev) of the free block at address a
-  __device__ __forceinline__ void set_link(uint32_t a, uint32_t f, uint32_t x) {
-    uint32_t ci, p;
-    Row r;
-    ta.locate(0u, a, ci, r, p);
-    ta.store_field(ta.slot(ci), p, f, x);
-  }
-  // Unlink block (a, s) with links (nx, pv) from its class list.
-  __device__ __forceinline__ void unlink(uint32_t s, uint32_t nx, uint32_t pv) {
-    const uint32_t c = cls(s);
+  // Unlink a block of sg granules with links (nx, pv) from its class list.
+  __device__ __forceinline__ void unlink(uint32_t sg, uint32_t nx, uint32_t pv) {
+    const uint32_t c = cls(sg);
     if (pv == kNone) {
       set_head(c, nx);
       if (nx == kNone) bit_clear(c);
     } else {
-      set_link(pv, 2u, nx);
+      rec_link(pv, 2u, nx);
     }
-    if (nx != kNone) set_link(nx, 3u, pv);
+    if (nx != kNone) rec_link(nx, 3u, pv);
   }
-  // Make block (a, s) the head of its class list (Alg. 4-5 push); returns
-  // the old head, the block's next link.
-  __device__ __forceinline__ uint32_t push(uint32_t a, uint32_t s) {
-    const uint32_t c = cls(s);
+  // Record i becomes the head of its class list (Alg. 4-5 push) with block
+  // (a, sg).
+  __device__ __forceinline__ void push(uint32_t i, uint32_t a, uint32_t sg) {
+    const uint32_t c = cls(sg);
     const uint32_t oh = head(c);
-    if (oh != kNone) set_link(oh, 3u, a);
-    set_head(c, a);
+    if (oh != kNone) rec_link(oh, 3u, i);
+    rec_put(i, a, sg, oh, kNone);
+    set_head(c, i);
     bit_set(c);
-    return oh;
   }
 
   // Alg. 6: one free block [0, A).
@@ -605,37 +647,39 @@ struct OrdHeap {
     ta.init(m.ta_l, m.ta_g, m.ta_n);
     F = 1; L = 0; rover = 0;
     hd = kNone; bm = 0ull; slb = 0u;
-    if constexpr (ALGO == kTlsf) {
-      for (uint32_t c = 0; c < kTlsfClasses; c += 64u) {
-        wave_sync();
-        m.heads[c + lane_id()] = kNone;
-      }
-    }
     if constexpr (kSeg) {
-      const uint32_t c = cls(ag);
-      set_head(c, 0u);
-      bit_set(c);
+      // records 0 .. capF - 1 are free, then record 0 takes the arena
+      const uint32_t base = 64u * lane_id();
+      frl = base >= capF ? 0u : (capF - base >= 32u ? ~0u : (1u << (capF - base)) - 1u);
+      frh = base + 32u >= capF ? 0u
+            : (capF - base - 32u >= 32u ? ~0u : (1u << (capF - base - 32u)) - 1u);
+      if constexpr (ALGO == kTlsf) {
+        for (uint32_t c = 0; c < kTlsfClasses; c += 64u) {
+          wave_sync();
+          m.heads[c + lane_id()] = kNone;
+        }
+      }
+      const uint32_t r0 = rec_take();
+      push(r0, 0u, ag);
+      ta.start(ag, r0);
+    } else {
+      frl = frh = 0u;
+      ta.start(ag, ag);
     }
-    ta.start(0u, ag, kNone, kNone);
     if constexpr (kKeys) {
       tb.init(m.tb_l, m.tb_g, m.tb_n);
-      tb.start(0u, ag, kNone, kNone);
+      tb.start(ag, ag);
     }
   }
 
-  // Commit an allocation of sg granules from block (a, s) at position p of
-  // chunk ci of the address table (row r just loaded); Alg. 1 / Alg. 4: the
-  // block is cut from the low end.
-  __device__ __forceinline__ int64_t commit(uint32_t ci, uint32_t p, const Row& r, uint32_t a,
-                                            uint32_t s, uint32_t sg) {
+  // First and next fit: the block at position p of chunk ci (row r current,
+  // key e = its end, value s = its size) gives sg granules from its low end.
+  __device__ __forceinline__ int64_t commit_fit(uint32_t ci, uint32_t p, const Row& r,
+                                                uint32_t e, uint32_t s, uint32_t sg) {
+    const uint32_t a = e - s;
     if (s > sg) {
-      const uint32_t sl = ta.slot(ci);
-      ta.store_entry(sl, p, a + sg, s - sg, kNone, kNone);
-      if (p == 0u) dir_put(ta.dk0, ci, a + sg);
-      if (kMax) {
-        const Row o = TA::pick(lane_id() == p, Row{a + sg, s - sg, kNone, kNone}, r);
-        dir_put(ta.dmx, ci, wave_max(o.s));
-      }
+      ta.store_field(ta.slot(ci), p, 1u, s - sg);  // the end stays
+      if (kMax) dir_put(ta.dmx, ci, wave_max(TA::with(r, p, e, s - sg).s));
     } else {
       ta.erase_at(ci, p, r);
       --F;
@@ -648,54 +692,68 @@ struct OrdHeap {
 
   // Allocate sg granules; kreq is the request's byte class (segregated fit)
   // or request class (TLSF).  Returns the byte offset, -1 or kENoMeta.
+  __device__ __forceinline__ bool full_dir() const {
+    return D < kOrdDir && (ta.nc >= 64u * D || (kKeys && tb.nc >= 64u * D));
+  }
+
+  // Continue a heap that ran with fewer directory registers: the same
+  // chunks, records and live entries, the directories widened.
+  template <int D1>
+  __device__ __forceinline__ void take(const OrdHeap<ALGO, D1>& o) {
+    widen(ta, o.ta);
+    if constexpr (kKeys) widen(tb, o.tb);
+    F = o.F; L = o.L; rover = o.rover;
+    hd = o.hd; bm = o.bm; slb = o.slb; frl = o.frl; frh = o.frh;
+  }
+  template <typename T2, typename T1>
+  __device__ __forceinline__ static void widen(T2& t, const T1& o) {
+    t.init(o.lb, o.gb, o.nl_req);
+#pragma unroll
+    for (int k = 0; k < T1::ND; ++k) {
+      t.dsl[k] = o.dsl[k]; t.dct[k] = o.dct[k]; t.dk0[k] = o.dk0[k]; t.dk1[k] = o.dk1[k];
+      t.dmx[k] = o.dmx[k]; t.used[k] = o.used[k];
+    }
+    t.nc = o.nc;
+  }
+
   __device__ __forceinline__ int64_t alloc(uint32_t sg, uint32_t kreq) {
     const uint32_t lane = lane_id();
+    if (full_dir()) return kOverflow;
     if constexpr (ALGO == kFirstFit) {
       const uint32_t ci = ta.first_fit_chunk(sg, 0u);
       if (ci == kNone) return kFail;
       const Row r = ta.load(ta.slot(ci));
       const uint32_t p = ctz64(ballot(r.s >= sg));
-      const uint32_t a = rdlane(r.a, p), s = rdlane(r.s, p);
+      const uint32_t e = rdlane(r.a, p), s = rdlane(r.s, p);
       if (L >= capL) return kENoMeta;
-      return commit(ci, p, r, a, s, sg);
+      return commit_fit(ci, p, r, e, s, sg);
     } else if constexpr (ALGO == kNextFit) {
-      // the search starts at the first block whose end lies past the rover:
-      // the last block starting at or below it, if it reaches past it, else
-      // the block after that one (R9-R11); then cyclically
+      // the search starts at the first block ending past the rover (R9-R11)
+      // and runs on cyclically: the rest of that chunk, the later chunks,
+      // then from the first chunk
       uint32_t ci0, p0;
       Row r0;
       ta.locate(0u, rover, ci0, r0, p0);
       uint32_t ci = kNone, p = 0;
       Row r;
+      bool found = false;
       if (ci0 != kNone) {
-        const uint32_t n = ta.count(ci0);
-        const uint64_t past = ballot(lane < n && r0.a + r0.s > rover);
-        // past != 0: its lowest lane is the start; else the start is the
-        // first entry of the next chunk
-        const uint32_t st = past != 0ull ? ctz64(past) : 64u;
-        const uint64_t fit = ballot(lane < n && lane >= st && r0.s >= sg);
-        if (fit != 0ull) {
-          ci = ci0; p = ctz64(fit); r = r0;
-        } else {
-          const uint32_t c1 = ta.first_fit_chunk(sg, ci0 + 1u);
-          const uint32_t c2 = c1 != kNone ? c1 : ta.first_fit_chunk(sg, 0u);
-          if (c2 == kNone) return kFail;
-          ci = c2;
-          r = c2 == ci0 ? r0 : ta.load(ta.slot(c2));
-          p = ctz64(ballot(lane < ta.count(c2) && r.s >= sg));
-        }
-      } else {
-        const uint32_t c2 = ta.first_fit_chunk(sg, 0u);
+        const uint64_t fit = ballot(lane < ta.count(ci0) && lane > p0 && r0.s >= sg);
+        if (fit != 0ull) { ci = ci0; p = ctz64(fit); r = r0; found = true; }
+      }
+      if (!found) {
+        const uint32_t c1 = ta.first_fit_chunk(sg, ci0 == kNone ? 0u : ci0 + 1u);
+        const uint32_t c2 = c1 != kNone ? c1 : ta.first_fit_chunk(sg, 0u);
         if (c2 == kNone) return kFail;
         ci = c2;
-        r = ta.load(ta.slot(c2));
+        r = c2 == ci0 ? r0 : ta.load(ta.slot(c2));
         p = ctz64(ballot(lane < ta.count(c2) && r.s >= sg));
       }
-      const uint32_t a = rdlane(r.a, p), s = rdlane(r.s, p);
+      const uint32_t e = rdlane(r.a, p), s = rdlane(r.s, p);
       if (L >= capL) return kENoMeta;
-      return commit(ci, p, r, a, s, sg);
+      return commit_fit(ci, p, r, e, s, sg);
     } else if constexpr (ALGO == kBestFit) {
-      // smallest key (size, address) at or above (sg, 0)
+      // smallest key (size, end) at or above (sg, 0)
       uint32_t ci, p;
       typename TB::Row r;
       tb.insert_pos(sg, 0u, ci, r, p);
@@ -705,15 +763,14 @@ struct OrdHeap {
         r = tb.load(tb.slot(ci));
         p = 0u;
       }
-      const uint32_t s = rdlane(r.s, p), a = rdlane(r.a, p);
-      if (s < sg) return kFail;  // (only an empty heap's sentinel-free chunk)
+      const uint32_t s = rdlane(r.s, p), e = rdlane(r.a, p);
       if (L >= capL) return kENoMeta;
       tb.erase_at(ci, p, r);
-      if (s > sg) tb.insert_key(a + sg, s - sg);
+      if (s > sg) tb.insert_key(e, s - sg);
       uint32_t cj, q;
       Row ra;
-      ta.locate(0u, a, cj, ra, q);
-      return commit(cj, q, ra, a, s, sg);
+      ta.locate(0u, e, cj, ra, q);
+      return commit_fit(cj, q, ra, e, s, sg);
     } else {
       // class of the first non-empty list at or above the request's
       uint32_t c;
@@ -735,28 +792,27 @@ struct OrdHeap {
         if (mk == 0ull) return kFail;
         c = ctz64(mk);
       }
-      const uint32_t a = head(c);
-      uint32_t ci, p;
-      Row r;
-      ta.locate(0u, a, ci, r, p);
-      const uint32_t s = rdlane(r.s, p), nx = rdlane(r.nx, p);
+      const uint32_t i = head(c);
+      const Rec b = rec(i);
       if (L >= capL) return kENoMeta;
       // pop the head (Alg. 4), keeping the lists' invariants (R20)
-      set_head(c, nx);
-      if (nx == kNone) bit_clear(c); else set_link(nx, 3u, kNone);
-      if (s > sg) {
-        // the remainder is pushed at the head of its class (Alg. 4)
-        const uint32_t oh = push(a + sg, s - sg);
-        ta.store_entry(ta.slot(ci), p, a + sg, s - sg, oh, kNone);
-        if (p == 0u) dir_put(ta.dk0, ci, a + sg);
+      set_head(c, b.nx);
+      if (b.nx == kNone) bit_clear(c); else rec_link(b.nx, 3u, kNone);
+      if (b.s > sg) {
+        // the remainder, same record and same end, is pushed at the head of
+        // its class (Alg. 4)
+        push(i, b.a + sg, b.s - sg);
       } else {
-        const Row rr = ta.load(ta.slot(ci));  // the links above may have changed it
-        ta.erase_at(ci, p, rr);
+        uint32_t ci, p;
+        Row r;
+        ta.locate(0u, b.a + b.s, ci, r, p);
+        ta.erase_at(ci, p, r);
+        rec_give(i);
         --F;
       }
-      lset(L, mk_ent(a, sg));
+      lset(L, mk_ent(b.a, sg));
       ++L;
-      return (int64_t)((uint64_t)a << shift);
+      return (int64_t)((uint64_t)b.a << shift);
     }
   }
 
@@ -765,84 +821,105 @@ struct OrdHeap {
   // entry would exceed the capacity.
   __device__ __forceinline__ bool release(uint32_t x, uint32_t sz) {
     const uint32_t lane = lane_id();
-    // the last free block below x and the one after it
+    const uint32_t xe = x + sz;
+    // the block ending at x (an exact key) and the block after x (the next
+    // entry, starting at xe if it borders)
     uint32_t ci, p;
     Row r;
     ta.locate(0u, x, ci, r, p);
-    bool hasL = false, hasR = false;
-    uint32_t la = 0, ls = 0, lnx = kNone, lpv = kNone;
-    uint32_t ra = 0, rs = 0, rnx = kNone, rpv = kNone;
-    uint32_t rci = 0, rp = 0;   // position of the block after x
-    if (ci != kNone) {
-      la = rdlane(r.a, p); ls = rdlane(r.s, p);
-      if (kSeg) { lnx = rdlane(r.nx, p); lpv = rdlane(r.pv, p); }
-      hasL = la + ls == x;
-      if (p + 1u < ta.count(ci)) {
-        rci = ci; rp = p + 1u;
-        ra = rdlane(r.a, rp); rs = rdlane(r.s, rp);
-        if (kSeg) { rnx = rdlane(r.nx, rp); rpv = rdlane(r.pv, rp); }
-        hasR = ra == x + sz;
-      } else if (ci + 1u < ta.nc && dir_get(ta.dk0, ci + 1u) == x + sz) {
-        rci = ci + 1u; rp = 0u;
-        const Row r2 = ta.load(ta.slot(rci));
-        ra = rdlane(r2.a, 0u); rs = rdlane(r2.s, 0u);
-        if (kSeg) { rnx = rdlane(r2.nx, 0u); rpv = rdlane(r2.pv, 0u); }
-        hasR = true;
+    const bool hasL = ci != kNone && rdlane(r.a, p) == x;
+    const uint32_t vl = ci != kNone ? rdlane(r.s, p) : 0u;  // size or record
+    // the entry after position p of chunk ci (ci = kNone: the first entry)
+    uint32_t rci = kNone, rp = 0;
+    Row rr = r;
+    if (ci != kNone && p + 1u < ta.count(ci)) {
+      rci = ci; rp = p + 1u;
+    } else {
+      const uint32_t nci = ci == kNone ? 0u : ci + 1u;
+      if (nci < ta.nc && ta.count(nci) != 0u) {
+        rci = nci; rp = 0u;
+        rr = ta.load(ta.slot(nci));
       }
-    } else if (ta.nc != 0u && ta.count(0u) != 0u && dir_get(ta.dk0, 0u) == x + sz) {
-      rci = 0u; rp = 0u;
-      const Row r2 = ta.load(ta.slot(0u));
-      ra = rdlane(r2.a, 0u); rs = rdlane(r2.s, 0u);
-      if (kSeg) { rnx = rdlane(r2.nx, 0u); rpv = rdlane(r2.pv, 0u); }
-      hasR = true;
+    }
+    const uint32_t er = rci != kNone ? rdlane(rr.a, rp) : 0u;
+    const uint32_t vr = rci != kNone ? rdlane(rr.s, rp) : 0u;
+    uint32_t sl = 0, sr = 0;
+    Rec bl{0, 0, kNone, kNone}, br{0, 0, kNone, kNone};
+    bool hasR;
+    if constexpr (kSeg) {
+      // both records are loaded before either is used
+      const u32x4 ql = rec_raw(hasL ? vl : 0u), qr = rec_raw(rci != kNone ? vr : 0u);
+      if (hasL) bl = rec_of(ql);
+      if (rci != kNone) br = rec_of(qr);
+      sl = bl.s;
+      sr = br.s;
+      hasR = rci != kNone && br.a == xe;
+    } else {
+      sl = vl;
+      sr = vr;
+      hasR = rci != kNone && er - vr == xe;
     }
     if (!hasL && !hasR && F >= capF) return false;
-    const uint32_t ma = hasL ? la : x;
-    const uint32_t ms = (hasL ? ls : 0u) + sz + (hasR ? rs : 0u);
-    uint32_t nx = kNone;
+    const uint32_t ma = hasL ? x - sl : x;
+    const uint32_t ms = (hasL ? sl : 0u) + sz + (hasR ? sr : 0u);
+    const uint32_t me = hasR ? er : xe;  // end of the merged block
     if constexpr (kSeg) {
       // unlink the free neighbours, then push the merged block (R21)
       if (hasL) {
-        unlink(ls, lnx, lpv);
+        unlink(sl, bl.nx, bl.pv);
         // unlinking the left block rewrote the links of its list
         // neighbours, which may include the right block
-        rpv = rpv == la ? lpv : rpv;
-        rnx = rnx == la ? lnx : rnx;
+        br.pv = br.pv == vl ? bl.pv : br.pv;
+        br.nx = br.nx == vl ? bl.nx : br.nx;
       }
-      if (hasR) unlink(rs, rnx, rpv);
-      nx = push(ma, ms);
+      if (hasR) unlink(sr, br.nx, br.pv);
     }
     if constexpr (kKeys) {
-      if (hasL) tb.erase_key(la, ls);
-      if (hasR) tb.erase_key(ra, rs);
-      tb.insert_key(ma, ms);
+      if (hasL) tb.erase_key(x, sl);
+      if (hasR) tb.erase_key(er, sr);
+      tb.insert_key(me, ms);
     }
-    if (hasL) {
-      ta.store_entry(ta.slot(ci), p, ma, ms, nx, kNone);
-      if (kMax) {
-        const Row o = TA::pick(lane == p, Row{ma, ms, kNone, kNone}, r);
-        dir_put(ta.dmx, ci, wave_max(o.s));
+    if (hasL && hasR) {
+      // the right block's entry keeps its end and takes the merged block;
+      // the left block's entry goes
+      if constexpr (kSeg) {
+        push(vr, ma, ms);
+        rec_give(vl);
+      } else {
+        ta.store_field(ta.slot(rci), rp, 1u, ms);
+        if (rci == ci) r = TA::with(r, rp, er, ms);  // the row erase_at shifts
+        else if (kMax) dir_put(ta.dmx, rci, wave_max(TA::with(rr, rp, er, ms).s));
       }
-      if (hasR) {
-        // the block after x: at rci / rp, still (entries were rewritten in
-        // place only)
-        const Row rr = ta.load(ta.slot(rci));
-        ta.erase_at(rci, rp, rr);
-        --F;
-      }
+      ta.erase_at(ci, p, r);
+      --F;
+    } else if (hasL) {
+      // the left block's entry: end x -> xe (its place does not change)
+      const uint32_t v = kSeg ? vl : ms;
+      ta.store_entry(ta.slot(ci), p, xe, v);
+      if (p == 0u) dir_put(ta.dk0, ci, xe);
+      if (kMax) dir_put(ta.dmx, ci, wave_max(TA::with(r, p, xe, ms).s));
+      if constexpr (kSeg) push(vl, ma, ms);
     } else if (hasR) {
-      ta.store_entry(ta.slot(rci), rp, ma, ms, nx, kNone);
-      if (rp == 0u) dir_put(ta.dk0, rci, ma);
-      if (kMax) dir_put(ta.dmx, rci, wave_max(ta.load(ta.slot(rci)).s));
+      // the right block grows downwards: its end and its entry stay
+      if constexpr (kSeg) {
+        push(vr, ma, ms);
+      } else {
+        ta.store_field(ta.slot(rci), rp, 1u, ms);
+        if (kMax) dir_put(ta.dmx, rci, wave_max(TA::with(rr, rp, er, ms).s));
+      }
     } else {
-      uint32_t ic, ip;
-      Row ir;
-      ta.insert_pos(0u, x, ic, ir, ip);
-      Row e = TA::sentinel();
-      e.a = x; e.s = sz; e.nx = nx; e.pv = kNone;
-      ta.insert_at(ic, ip, ir, e);
+      // a new entry right after position p (ci = kNone: first of chunk 0)
+      uint32_t v = sz;
+      if constexpr (kSeg) {
+        v = rec_take();
+        push(v, x, sz);
+      }
+      const uint32_t ic = ci == kNone ? 0u : ci, ip = ci == kNone ? 0u : p + 1u;
+      const Row ir = ci == kNone ? (rci == 0u ? rr : ta.load(ta.slot(0u))) : r;
+      ta.insert_at(ic, ip, ir, Row{xe, v});
       ++F;
     }
+    (void)lane;
     return true;
   }
 
@@ -850,7 +927,13 @@ struct OrdHeap {
   // (partial deallocation, sequential fits; cut < 2^31).  Returns the byte
   // offset of the released part or kENoMeta.
   __device__ __forceinline__ int64_t free_index(uint32_t idx, uint32_t cut) {
-    const Ent v = lget(idx);
+    if (full_dir()) return kOverflow;
+    const uint32_t last = L - 1u;
+    // both entries are loaded before either is used, so their latencies
+    // overlap
+    const Ent v0 = lraw(idx), w0 = lraw(last);
+    const Ent v = mk_ent(uniform(ent_a(v0)), uniform(ent_s(v0)));
+    const Ent w = mk_ent(uniform(ent_a(w0)), uniform(ent_s(w0)));
     const uint32_t bx = ent_a(v), bsz = ent_s(v);
     const uint32_t t = (kSeg || cut == 0u) ? 0u : (uint32_t)(((uint64_t)cut * bsz) >> 31);
     const uint32_t x = bx + t, sz = bsz - t;
@@ -858,9 +941,7 @@ struct OrdHeap {
     if (t != 0u) {
       lset(idx, mk_ent(bx, t));
     } else {
-      const uint32_t last = L - 1u;
-      const Ent e = lget(last);
-      lset(idx, e);
+      lset(idx, w);
       L = last;
     }
     return (int64_t)((uint64_t)x << shift);
@@ -885,10 +966,20 @@ struct OrdHeap {
     for (uint32_t ci = 0; ci < ta.nc; ++ci) {
       const Row r = ta.load(ta.slot(ci));
       const uint32_t n = ta.count(ci);
+      uint32_t a = r.a - r.s, s = r.s;
+      if constexpr (kSeg) {
+        // this lane's record (lanes past the chunk read record 0, unused)
+        wave_sync();
+        const uint32_t i = lane < n && r.s < kOrdMaxFree ? r.s : 0u;
+        u32x4 v;
+        if (i < m.rec_n) v = m.rec_l[i]; else v = m.rec_g[i];
+        a = v[0];
+        s = v[1];
+      }
       wave_sync();
       if (lane < n) {
-        fo[2 * (k + lane)] = (int64_t)((uint64_t)r.a << sh);
-        fo[2 * (k + lane) + 1] = (int64_t)((uint64_t)r.s << sh);
+        fo[2 * (k + lane)] = (int64_t)((uint64_t)a << sh);
+        fo[2 * (k + lane) + 1] = (int64_t)((uint64_t)s << sh);
       }
       k += n;
     }
@@ -912,7 +1003,8 @@ struct OrdHeap {
     }
     if constexpr (kSeg) {
       // each class: its length, then its blocks from the head along the
-      // next links
+      // next links (bounded by the section's words even if a list were
+      // corrupt)
       int64_t* ls = tail + 2;
       uint32_t pos = 0;
       for (uint32_t c = 0; c < (uint32_t)lists; ++c) {
@@ -921,15 +1013,12 @@ struct OrdHeap {
         else nonempty = (bm >> c) & 1ull;
         uint32_t n = 0;
         if (nonempty) {
-          uint32_t a = head(c);
-          // (bounded by the section's words even if a list were corrupt)
-          while (a != kNone && pos + 1u + n < (uint32_t)lists + F) {
+          uint32_t i = head(c);
+          while (i != kNone && pos + 1u + n < (uint32_t)lists + F) {
+            const Rec b = rec(i);
             wave_sync();
-            if (lane == 0) ls[pos + 1u + n] = (int64_t)((uint64_t)a << sh);
-            uint32_t ci, p;
-            Row r;
-            ta.locate(0u, a, ci, r, p);
-            a = rdlane(r.nx, p);
+            if (lane == 0) ls[pos + 1u + n] = (int64_t)((uint64_t)b.a << sh);
+            i = b.nx;
             ++n;
           }
         }

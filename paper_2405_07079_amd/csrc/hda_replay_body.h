@@ -244,11 +244,20 @@ template <int ALGO>
 __device__ __forceinline__ void ord_replay_heap(const ReplayParams& p, HDA_LDS uint8_t* pool,
                                 HDA_GLOBAL uint8_t* dev, const HeapRegs& regs, int64_t heap) {
   const OrdMem m = ord_mem(ALGO, pool, p.ord_pool_bytes, p.ord_slot_bytes, dev, p.cap_live);
-  OrdHeap<ALGO> w(m, regs, p.cap_free, p.cap_live);
+  // one directory register while the tables fit 64 chunks, then two
+  OrdHeap<ALGO, 1> w(m, regs, p.cap_free, p.cap_live);
   w.init();
   int32_t st = 0;
-  run_requests<ALGO>(p, w, p.req_off[heap], p.req_off[heap + 1], regs.shift, regs.arena, st);
-  finish_heap(p, w, heap, st);
+  const int64_t b1 = p.req_off[heap + 1];
+  const int64_t pos = run_requests<ALGO>(p, w, p.req_off[heap], b1, regs.shift, regs.arena, st);
+  if (pos == b1) {
+    finish_heap(p, w, heap, st);
+    return;
+  }
+  OrdHeap<ALGO, kOrdDir> w2(m, regs, p.cap_free, p.cap_live);
+  w2.take(w);
+  run_requests<ALGO>(p, w2, pos, b1, regs.shift, regs.arena, st);
+  finish_heap(p, w2, heap, st);
 }
 
 __device__ __forceinline__ void ord_any_heap(const ReplayParams& p, HDA_LDS uint8_t* pool,
