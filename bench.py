@@ -30,6 +30,8 @@ sys.path.insert(0, ROOT)
 METRIC = ("alloc+free ops/s on 1 MI355X (batched vs per-heap replay); "
           "p50/p99 req latency")
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
+# the service's stated latency bound and the rate up to which it is stated
+P99_BOUND_US, P99_BOUND_RATE = 200.0, 1e7
 BYTES_PER_REQUEST = 16         # 8 B request read + 8 B result written
 # MI355X instruction issue: 256 CUs x 4 SIMDs, 2.4 GHz; a wave64 VALU
 # instruction takes 4 cycles on a 16-lane SIMD; one scalar unit per CU
@@ -148,6 +150,56 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def median_time(fn, runs=3):
+    """Median wall time of `runs` calls of fn() (seconds)."""
+    ts = []
+    for _ in range(runs):
+        t = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t)
+    return float(np.median(ts))
+
+
+def event_ms(torch, stream, fn, runs):
+    """Durations (ms) of `runs` calls of fn(), each bracketed by HIP events
+    recorded on `stream` (the stream the work is enqueued on)."""
+    evs = []
+    for _ in range(runs):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in evs]
+
+
+def device_info(torch):
+    """What the device reports about itself (torch's hipDeviceProp view)."""
+    pr = torch.cuda.get_device_properties(0)
+    out = {}
+    for k in ("name", "gcnArchName", "multi_processor_count", "shared_memory_per_block",
+              "L2_cache_size", "total_memory", "warp_size", "regs_per_multiprocessor"):
+        v = getattr(pr, k, None)
+        out[k] = v if isinstance(v, (int, float, str)) or v is None else str(v)
+    return out
+
+
+def host_info():
+    """Host CPU model and the threads this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "affinity": host_cores()}
+
+
 def host_cores():
     try:
         return len(os.sched_getaffinity(0))
@@ -248,6 +300,172 @@ def paper_analog(W, torch):
     return out
 
 
+# bytes the paper's own structures move per metadata touch: a free-list
+# entry as (u32 address, u32 size) in granules; a segregated-fit record as
+# address, size, prev_adj, next, prev and the free flag in u32 fields
+ENTRY_BYTES, RECORD_BYTES = 8, 24
+
+
+def oracle_metadata_bytes(stats, requests):
+    """Metadata bytes per request the method itself touches, from the
+    oracle's pinned counters (entries a fit search inspects, records the
+    segregated-fit lists read or write)."""
+    ex = float(stats[:, 0].sum())
+    to = float(stats[:, 1].sum())
+    return (ENTRY_BYTES * ex + RECORD_BYTES * to) / max(1, requests)
+
+
+def leg_c1(W, hda, oracle, torch, stream):
+    """One 64 KiB heap (16 B alignment), 10,000 requests, one wavefront:
+    ns per request for every algorithm (first fit is the configuration as
+    stated; the others run the same trace)."""
+    base = W.single_heap()
+    out = {"workload": "1 heap, 64 KiB arena, 16 B alignment, 10,000 requests (alloc p=0.6, "
+                       "sizes log-uniform 16 B-4 KiB), one wavefront per launch",
+           "unit": "ns/request", "per_algorithm": {}, "cpu_baseline": {}}
+    for algo in range(5):
+        b = base.with_algo(algo)
+        db = hda.upload(b)
+        hda.hda_replay(db, stream)
+        torch.cuda.synchronize()
+        if int((db.status != 0).sum().item()):
+            raise RuntimeError("single-heap leg: heap reported an error")
+        ms = float(np.median(event_ms(torch, stream, lambda: hda.hda_replay(db, stream), 7)))
+        name = W.ALGO_NAMES[algo]
+        out["per_algorithm"][name] = ms * 1e6 / b.requests
+        req = np.ascontiguousarray(b.req)
+        ct = median_time(lambda: oracle.replay_heap(algo, int(b.arena[0]), int(b.align[0]), req))
+        out["cpu_baseline"][name] = ct * 1e9 / b.requests
+        del db
+    out["value"] = out["per_algorithm"]["first_fit"]
+    out["cpu_baseline"].update({"unit": "ns/request", "cores": 1, "kind": "oracle",
+                                "sample": "the whole trace, median of 3"})
+    return out
+
+
+def leg_c3(W, hda, oracle, torch, stream, cores):
+    """The uneven batch (16,384 heaps, arenas 1 MiB-1 GiB, Pareto trace
+    lengths, four algorithms) in longest-first order: default tuning, the
+    autotuner's choice, and that choice launched as a captured graph;
+    per-heap launches on a sample."""
+    t0 = time.perf_counter()
+    b = W.uneven_batch()
+    log(f"[bench] c3: generated {b.requests} requests in {time.perf_counter() - t0:.1f} s")
+    db = hda.upload(b)
+    run = lambda: hda.hda_replay(db, stream)  # noqa: E731
+    run()
+    torch.cuda.synchronize()
+    default_ms = float(np.median(event_ms(torch, stream, run, 3)))
+    t0 = time.perf_counter()
+    tune = hda.hda_replay_autotune(db, 0, stream)
+    tune_s = time.perf_counter() - t0
+    hda.retune(db, tune)
+    run()
+    torch.cuda.synchronize()
+    tuned_ms = float(np.median(event_ms(torch, stream, run, 3)))
+    g = hda.ReplayGraph(db)
+    try:
+        g.launch(stream)
+        torch.cuda.synchronize()
+        graph_ms = float(np.median(event_ms(torch, stream, lambda: g.launch(stream), 3)))
+    finally:
+        g.close()
+    if int((db.status != 0).sum().item()):
+        raise RuntimeError("uneven-batch leg: heaps reported errors")
+    resolved = hda.hda_replay_resolve(db)
+    del db
+    # one launch per heap on a sample of 256 heaps (every 64th heap)
+    idx = np.arange(0, b.heaps, 64)
+    sub = b.subset(idx)
+    sdb = hda.upload(sub)
+    hda.hda_replay_per_heap(sdb, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hda.hda_replay_per_heap(sdb, stream)
+    torch.cuda.synchronize()
+    ph = sub.requests / (time.perf_counter() - t1)
+    del sdb
+    ct = median_time(lambda: oracle.replay_batch(b, threads=cores, want_state=False))
+    ops = lambda ms: b.requests / (ms / 1e3)  # noqa: E731
+    return {"workload": f"{b.heaps} heaps, arenas log-uniform 1 MiB-1 GiB (32 B alignment), "
+                        f"trace lengths Pareto(1.5) clipped to 1k-1M ({b.requests} requests), "
+                        "first/next/best/segregated fit uniformly, longest first",
+            "unit": "ops/s", "value": ops(graph_ms),
+            "default": {"ms": default_ms, "ops_s": ops(default_ms)},
+            "autotuned": {"ms": tuned_ms, "ops_s": ops(tuned_ms), "tuning": resolved,
+                          "autotune_s": tune_s},
+            "autotuned_graph": {"ms": graph_ms, "ops_s": ops(graph_ms)},
+            "per_heap_launch": {"value": ph, "unit": "ops/s",
+                                "sample": f"{sub.heaps} heaps (every 64th), {sub.requests} "
+                                          "requests, one launch per heap"},
+            "cpu_baseline": {"value": b.requests / ct, "unit": "ops/s", "cores": cores,
+                             "kind": "oracle",
+                             "sample": f"the whole batch, median of 3 ({ct:.1f} s)"}}
+
+
+def leg_c5(W, hda, oracle, torch, stream):
+    """The 256 GiB segregated-fit heap (4 KiB granules), 50 M requests, on
+    the ordered core (one wavefront with the whole LDS of a workgroup)."""
+    import hashlib
+    t0 = time.perf_counter()
+    b = W.large_seg_fit()
+    log(f"[bench] c5: generated {b.requests} requests in {time.perf_counter() - t0:.1f} s")
+    tu = hda.tuning(heavy_heaps=1, heavy_kib=158)
+    db = hda.upload(b, tuning=tu, meta_free=4096, meta_live=16384)
+    ms = event_ms(torch, stream, lambda: hda.hda_replay(db, stream), 1)[0]
+    status = int(db.status[0].item())
+    if status:
+        raise RuntimeError(f"256 GiB leg: status {status}")
+    digest_ok = None
+    gp = os.path.join(ROOT, "tests", "golden", "large_seg_fit_256GiB.json")
+    if os.path.exists(gp):
+        with open(gp) as f:
+            g = json.load(f)
+        res = db.res.cpu().numpy()
+        digest_ok = hashlib.sha256(np.ascontiguousarray(res, "<i8").tobytes()).hexdigest() == \
+            g["results_sha256"]
+    resolved = hda.hda_replay_resolve(db)
+    del db
+    n = 2_000_000
+    req = np.ascontiguousarray(b.req[:n])
+    ct = median_time(lambda: oracle.replay_heap(W.SEG_FIT, int(b.arena[0]), int(b.align[0]), req))
+    return {"workload": "1 heap, 256 GiB virtual arena, 4 KiB granules, segregated fit, 50 M "
+                        "requests (alloc p=0.5, sizes geometric over the 4 KiB-64 MiB classes), "
+                        "replayed in order by one wavefront",
+            "unit": "ops/s", "value": b.requests / (ms / 1e3), "ms": ms,
+            "ns_per_request": ms * 1e6 / b.requests, "tuning": resolved,
+            "results_equal_oracle_digest": digest_ok,
+            "cpu_baseline": {"value": n / ct, "unit": "ops/s", "cores": 1, "kind": "oracle",
+                             "sample": f"the first {n} requests, median of 3"}}
+
+
+def leg_serving(hda, rates, clients, seconds, bound_us, bound_rate):
+    """The device-resident service under open-loop Poisson load from
+    `clients` clients (one heap each) at each rate: throughput and latency
+    percentiles from arrival to completion."""
+    srv = hda.Server(max_heaps=clients + 16, max_seconds=600)
+    by_rate = []
+    try:
+        for rate in rates:
+            rep, _ = srv.load(clients=clients, rate=rate, warmup_s=0.5, measure_s=seconds,
+                              threads=8)
+            if rep["errors"]:
+                raise RuntimeError(f"serving leg reported {rep['errors']} errors at {rate:g}/s")
+            by_rate.append({"offered_rate": rate, "throughput": rep["throughput"],
+                            "p50_us": rep["p50_us"], "p90_us": rep["p90_us"],
+                            "p99_us": rep["p99_us"], "p999_us": rep["p999_us"],
+                            "max_us": rep["max_us"], "completed": rep["completed"],
+                            "alloc_fail": rep["alloc_fail"], "window_s": rep["window_s"]})
+            log(f"[bench] serving at {rate:.3g}/s: {rep['throughput']:.3g}/s, "
+                f"p50 {rep['p50_us']:.1f} us, p99 {rep['p99_us']:.1f} us")
+    finally:
+        srv.stop()
+    within = [r["p99_us"] <= bound_us for r in by_rate if r["offered_rate"] <= bound_rate]
+    return {"clients": clients, "unit": "requests/s",
+            "p99_bound_us": bound_us, "bound_rate": bound_rate,
+            "within_bound": bool(within) and all(within), "by_rate": by_rate}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,8 +478,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1024,
                     help="heaps per algorithm replayed by the CPU oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-rate", type=float, default=1e7,
-                    help="serving leg: open-loop arrivals per second (0 = skip)")
+    ap.add_argument("--serve-rates", type=str, default="1e6,2e6,5e6,1e7,2e7",
+                    help="serving leg: open-loop arrival rates per second, comma-separated "
+                         "(empty or 0 = skip)")
     ap.add_argument("--serve-clients", type=int, default=100_000)
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="serving leg: measured window (after 0.5 s of warmup)")
@@ -277,6 +496,12 @@ def main():
     ap.add_argument("--partial-frees", type=float, default=0.02,
                     help="fraction of frees that are partial (Alg. 2) in the partial-"
                          "deallocation leg, a best-fit batch of the same shape (0: skip)")
+    ap.add_argument("--no-c1", action="store_true",
+                    help="skip the single 64 KiB heap leg")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the uneven-batch leg (16,384 heaps)")
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the 256 GiB single-heap leg (50 M requests)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (a kernel of "
                          "known traffic for scaling memory counters)")
@@ -461,27 +686,14 @@ def main():
             f"{partial['value'] / 1e9:.3f} G ops/s")
 
     serving = None
-    if args.serve_rate > 0:
+    rates = [float(x) for x in args.serve_rates.split(",") if x.strip() and float(x) > 0]
+    if rates:
         # device-resident service: one heap per client (64 MiB-4 GiB, 512 B
         # alignment, segregated fit), Poisson arrivals, 70 % power-of-two sizes
         # 512 B-256 MiB and 30 % log-uniform, exponential lifetimes (mean 500
-        # requests); latency from submission to completion seen by the client
-        srv = hda.Server(max_heaps=args.serve_clients + 16, max_seconds=600)
-        try:
-            rep, _ = srv.load(clients=args.serve_clients, rate=args.serve_rate, warmup_s=0.5,
-                              measure_s=args.serve_seconds, threads=8)
-        finally:
-            srv.stop()
-        if rep["errors"]:
-            raise RuntimeError(f"serving leg reported {rep['errors']} errors")
-        serving = {"offered_rate": args.serve_rate, "clients": args.serve_clients,
-                   "throughput": rep["throughput"], "unit": "requests/s",
-                   "p50_us": rep["p50_us"], "p99_us": rep["p99_us"],
-                   "p999_us": rep["p999_us"], "max_us": rep["max_us"],
-                   "window_s": rep["window_s"], "completed": rep["completed"],
-                   "alloc_fail": rep["alloc_fail"]}
-        log(f"[bench] serving at {args.serve_rate:.3g}/s: {rep['throughput']:.3g}/s, "
-            f"p50 {rep['p50_us']:.1f} us, p99 {rep['p99_us']:.1f} us")
+        # requests); latency from arrival to completion seen by the client
+        serving = leg_serving(hda, rates, args.serve_clients, args.serve_seconds,
+                              P99_BOUND_US, P99_BOUND_RATE)
 
     analog = None
     if not args.no_paper_analog:
@@ -490,56 +702,57 @@ def main():
             f"hipMalloc p50 {analog['vendor']['alloc_p50_us']:.1f} us")
 
     cpu = None
+    meta_oracle = None
     if not args.no_cpu_baseline:
         import oracle
         cores = host_cores()
         C = min(args.cpu_sample, batch.heaps)
         csub = batch.subset(np.arange(C))
-        t1 = time.perf_counter()
-        for algo in algos:
-            oracle.replay_batch(csub.with_algo(algo), threads=cores, want_state=True)
-        ct = time.perf_counter() - t1
+        ct = median_time(lambda: [oracle.replay_batch(csub.with_algo(a), threads=cores,
+                                                      want_state=True) for a in algos])
+        # the method's own metadata bytes per request, from the oracle's
+        # pinned counters on the same sample
+        meta_oracle = {}
+        for a in algos:
+            _, _, st = oracle.replay_batch(csub.with_algo(a), threads=cores, want_state=False,
+                                           want_stats=True)
+            meta_oracle[W.ALGO_NAMES[a]] = oracle_metadata_bytes(st, csub.requests)
         one = batch.subset(np.arange(min(16, C)))
-        t1 = time.perf_counter()
-        for algo in algos:
-            oracle.replay_batch(one.with_algo(algo), threads=1, want_state=True)
-        c1 = time.perf_counter() - t1
+        c1t = median_time(lambda: [oracle.replay_batch(one.with_algo(a), threads=1,
+                                                       want_state=True) for a in algos])
         cpu = {"value": csub.requests * len(algos) / ct, "unit": "ops/s", "cores": cores,
-               "value_1_thread": one.requests * len(algos) / c1,
+               "value_1_thread": one.requests * len(algos) / c1t,
                "kind": "oracle",
                "sample": f"first {C} heaps of the batch x (best fit, seg fit), "
-                         f"{csub.requests * len(algos)} requests, {ct:.1f} s wall "
-                         f"on {cores} threads"}
+                         f"{csub.requests * len(algos)} requests, median of 3 "
+                         f"({ct:.1f} s wall on {cores} threads)"}
         log(f"[bench] cpu oracle: {cpu['value'] / 1e6:.2f} M ops/s on {cores} threads")
-        if bitmap is not None:
-            bsub = csub.with_algo(W.BITMAP)
-            t1 = time.perf_counter()
-            oracle.replay_batch(bsub, threads=cores, want_state=True)
-            bt = time.perf_counter() - t1
-            bitmap["cpu_baseline"] = {"value": bsub.requests / bt, "unit": "ops/s",
-                                      "cores": cores, "kind": "oracle",
-                                      "sample": f"first {bsub.heaps} heaps, {bsub.requests} "
-                                                f"requests, {bt:.1f} s wall"}
-        if tlsf is not None:
-            tsub = csub.with_algo(W.TLSF)
-            t1 = time.perf_counter()
-            oracle.replay_batch(tsub, threads=cores, want_state=True)
-            tt = time.perf_counter() - t1
-            tlsf["cpu_baseline"] = {"value": tsub.requests / tt, "unit": "ops/s",
-                                    "cores": cores, "kind": "oracle",
-                                    "sample": f"first {tsub.heaps} heaps, {tsub.requests} "
-                                              f"requests, {tt:.1f} s wall"}
-        if partial is not None:
-            psub = pb.subset(np.arange(min(256, pb.heaps)))
-            t1 = time.perf_counter()
-            oracle.replay_batch(psub, threads=cores, want_state=True)
-            pt = time.perf_counter() - t1
-            partial["cpu_baseline"] = {"value": psub.requests / pt, "unit": "ops/s",
-                                       "cores": cores, "kind": "oracle",
-                                       "sample": f"first {psub.heaps} heaps, {psub.requests} "
-                                                 f"requests, {pt:.1f} s wall"}
+        small = batch.subset(np.arange(min(256, batch.heaps)))
+        for leg, sb in ((bitmap, small.with_algo(W.BITMAP)), (tlsf, small.with_algo(W.TLSF)),
+                        (partial, None if partial is None else
+                         pb.subset(np.arange(min(256, pb.heaps))))):
+            if leg is None:
+                continue
+            t = median_time(lambda: oracle.replay_batch(sb, threads=cores, want_state=True))
+            leg["cpu_baseline"] = {"value": sb.requests / t, "unit": "ops/s", "cores": cores,
+                                   "kind": "oracle",
+                                   "sample": f"first {sb.heaps} heaps, {sb.requests} "
+                                             f"requests, median of 3"}
+
+    import oracle as _oracle
+    c1 = None if args.no_c1 else leg_c1(W, hda, _oracle, torch, stream)
+    if c1:
+        log(f"[bench] c1: {c1['per_algorithm']}")
+    c3 = None if args.no_c3 else leg_c3(W, hda, _oracle, torch, stream, host_cores())
+    if c3:
+        log(f"[bench] c3: default {c3['default']['ops_s'] / 1e6:.1f} M, autotuned "
+            f"{c3['autotuned']['ops_s'] / 1e6:.1f} M, graph {c3['value'] / 1e6:.1f} M ops/s")
+    c5 = None if args.no_c5 else leg_c5(W, hda, _oracle, torch, stream)
+    if c5:
+        log(f"[bench] c5: {c5['value'] / 1e6:.2f} M ops/s ({c5['ms'] / 1e3:.1f} s)")
 
     traffic = recorded_traffic([W.ALGO_NAMES[a] for a in algos])
+    state_bytes = float(np.mean([int(dbs[a].state_len.sum().item()) * 8 for a in algos]))
     out = {
         "metric": METRIC,
         "value": value,
@@ -573,8 +786,14 @@ def main():
                      "traffic_unit": "bytes per launch",
                      "traffic_frac": (None if traffic is None else
                                       traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS),
-                     # free and live tables stay in VGPRs and LDS for this workload
-                     "metadata_hbm_bytes_per_request": 0,
+                     # HBM bytes beyond the requests, results and state dumps
+                     "metadata_hbm_bytes_per_request": (
+                         None if traffic is None else
+                         max(0.0, (traffic - BYTES_PER_REQUEST * batch.requests
+                                   - state_bytes) / batch.requests)),
+                     # what the method's own structures would touch per request
+                     # (oracle counters; 8 B per list entry, 24 B per record)
+                     "metadata_bytes_per_request_oracle": meta_oracle,
                      "lds_bank_conflict_cycles_per_request": recorded_lds_conflicts(),
                      # what bounds this kernel: instruction issue (see DESIGN)
                      "issue": issue_roofline(per_algo),
@@ -587,6 +806,11 @@ def main():
         "partial_free": partial,
         "paper_analog": analog,
         "serving": serving,
+        "c1": c1,
+        "c3": c3,
+        "c5": c5,
+        "device": device_info(torch),
+        "host": host_info(),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

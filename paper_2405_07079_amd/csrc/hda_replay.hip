@@ -588,55 +588,30 @@ static std::vector<int32_t> longest_heaps(const std::vector<int64_t>& off, int64
   return out;
 }
 
-int hda_replay_autotune(const hda_batch_desc* d, int32_t sample_heaps, void* stream,
-                        hda_tuning* out) {
-  constexpr int64_t kCut = 65536, kBudget = int64_t(16) << 20;
-  Plan pl;
-  if (!out || !desc_ok(d) || sample_heaps < 0 || !make_plan(d, true, &pl)) return HDA_E_INVAL;
-  DeviceCtx* dc = device_ctx();
-  if (!dc) return HDA_E_DEVICE;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const int64_t H = d->n_heaps;
-  if (H == 0) return hda_replay_resolve(d, out);
-  // heap parameters and trace lengths on the host
-  std::vector<int64_t> off(H + 1), arena(H), align(H);
-  std::vector<int32_t> algo(H);
-  if (hipMemcpyAsync(off.data(), d->req_off, off.size() * 8, hipMemcpyDeviceToHost, s) !=
-          hipSuccess ||
-      hipMemcpyAsync(arena.data(), d->arena, H * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(align.data(), d->align, H * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(algo.data(), d->algo, H * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return HDA_E_DEVICE;
-  // sample: the longest heaps, as many as the device holds at once under the
-  // default tuning, each trace cut to its first kCut requests
-  const int64_t want = sample_heaps > 0 ? sample_heaps : pl.main.slots;
-  const std::vector<int32_t> sample = longest_heaps(off, want, dc->cus, kBudget, kCut);
+}  // extern "C"
+
+namespace {
+
+// Time each candidate tuning on a private batch made of the heaps in
+// `sample` (indices into the caller's batch), each trace cut to `cut`
+// requests, in that order (one untimed trial first).  *pick receives the
+// fastest candidate.
+int time_candidates(const hda_batch_desc* d, const std::vector<int64_t>& off,
+                    const std::vector<int64_t>& arena, const std::vector<int64_t>& align,
+                    const std::vector<int32_t>& algo, const std::vector<int32_t>& sample,
+                    int64_t cut, const std::vector<hda_tuning>& cand, hipStream_t s,
+                    hda_tuning* pick) {
   const int64_t S = (int64_t)sample.size();
   std::vector<int64_t> s_off(S + 1, 0), s_arena(S), s_align(S);
   std::vector<int32_t> s_algo(S);
   for (int64_t k = 0; k < S; ++k) {
     const int32_t h = sample[k];
-    s_off[k + 1] = s_off[k] + std::min(off[h + 1] - off[h], kCut);
+    s_off[k + 1] = s_off[k] + std::min(off[h + 1] - off[h], cut);
     s_arena[k] = arena[h];
     s_align[k] = align[h];
     s_algo[k] = algo[h];
   }
   const int64_t N = std::max<int64_t>(s_off[S], 1);
-  // candidates: heaps per workgroup x LDS residency of the lean path
-  std::vector<hda_tuning> cand;
-  const uint32_t lds_pairs[][2] = {{64, 512}, {128, 1024}, {256, 2048}, {512, 4096}};
-  for (int32_t W : {1, 2, 4, 8, 16})
-    for (const auto& kv : lds_pairs) {
-      hda_tuning t = d->tuning;
-      t.heaps_per_group = W;
-      t.reg_free = t.reg_free < 0 ? 0 : t.reg_free;
-      t.reg_live = 0;
-      t.lds_free = (int32_t)kv[0];
-      t.lds_live = (int32_t)kv[1];
-      t.groups = 0;
-      cand.push_back(t);
-    }
   // the trial batch: its own buffers, so the caller's outputs are untouched
   hda_batch_desc dd;
   std::memset(&dd, 0, sizeof(dd));
@@ -653,7 +628,7 @@ int hda_replay_autotune(const hda_batch_desc* d, int32_t sample_heaps, void* str
       ws = std::max(ws, p2.bytes);
     }
   }
-  if (ok.empty()) return hda_replay_resolve(d, out);
+  if (ok.empty()) return HDA_E_INVAL;
   auto up = [](size_t x) { return (x + 255) / 256 * 256; };
   const size_t o_arena = 0, o_align = up(o_arena + S * 8), o_algo = up(o_align + S * 8),
                o_off = up(o_algo + S * 4), o_req = up(o_off + (S + 1) * 8),
@@ -663,7 +638,7 @@ int hda_replay_autotune(const hda_batch_desc* d, int32_t sample_heaps, void* str
   hipEvent_t e0 = nullptr, e1 = nullptr;
   int rc = HDA_E_DEVICE;
   float best = -1.0f;
-  hda_tuning pick = ok[0];
+  *pick = ok[0];
   buf = static_cast<uint8_t*>(dev_alloc(bytes));
   if (buf && hipEventCreate(&e0) == hipSuccess &&
       hipEventCreate(&e1) == hipSuccess &&
@@ -703,7 +678,7 @@ int hda_replay_autotune(const hda_batch_desc* d, int32_t sample_heaps, void* str
       if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = HDA_E_DEVICE;
       if (i > 0 && (best < 0.0f || ms < best)) {
         best = ms;
-        pick = ok[i - 1];
+        *pick = ok[i - 1];
       }
     }
   }
@@ -713,7 +688,82 @@ int hda_replay_autotune(const hda_batch_desc* d, int32_t sample_heaps, void* str
     (void)hipStreamSynchronize(s);
     dev_free(buf);
   }
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hda_replay_autotune(const hda_batch_desc* d, int32_t sample_heaps, void* stream,
+                        hda_tuning* out) {
+  constexpr int64_t kCut = 65536, kBudget = int64_t(16) << 20;
+  constexpr int64_t kHeavyCut = int64_t(1) << 20;
+  Plan pl;
+  if (!out || !desc_ok(d) || sample_heaps < 0 || !make_plan(d, true, &pl)) return HDA_E_INVAL;
+  DeviceCtx* dc = device_ctx();
+  if (!dc) return HDA_E_DEVICE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t H = d->n_heaps;
+  if (H == 0) return hda_replay_resolve(d, out);
+  // heap parameters and trace lengths on the host
+  std::vector<int64_t> off(H + 1), arena(H), align(H);
+  std::vector<int32_t> algo(H);
+  if (hipMemcpyAsync(off.data(), d->req_off, off.size() * 8, hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(arena.data(), d->arena, H * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(align.data(), d->align, H * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(algo.data(), d->algo, H * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return HDA_E_DEVICE;
+  // 1. heaps per workgroup and the lean path's LDS residency, on the longest
+  // heaps, as many as the device holds at once under the default tuning,
+  // each trace cut to its first kCut requests
+  const int64_t want = sample_heaps > 0 ? sample_heaps : pl.main.slots;
+  const std::vector<int32_t> sample = longest_heaps(off, want, dc->cus, kBudget, kCut);
+  std::vector<hda_tuning> cand;
+  const uint32_t lds_pairs[][2] = {{64, 512}, {128, 1024}, {256, 2048}, {512, 4096}};
+  for (int32_t W : {1, 2, 4, 8, 16})
+    for (const auto& kv : lds_pairs) {
+      hda_tuning t = d->tuning;
+      t.heaps_per_group = W;
+      t.reg_free = t.reg_free < 0 ? 0 : t.reg_free;
+      t.reg_live = 0;
+      t.lds_free = (int32_t)kv[0];
+      t.lds_live = (int32_t)kv[1];
+      t.groups = 0;
+      t.heavy_heaps = 0;
+      t.heavy_kib = 0;
+      cand.push_back(t);
+    }
+  hda_tuning pick;
+  int rc = time_candidates(d, off, arena, align, algo, sample, kCut, cand, s, &pick);
+  if (rc == HDA_E_INVAL) return hda_replay_resolve(d, out);
   if (rc != HDA_OK) return rc;
+  // 2. how many of the longest heaps the ordered core takes (0, 16, 64,
+  // 128, or every sampled heap when fewer), timed on the 128 longest heaps
+  // with traces up to kHeavyCut requests, so that their tables reach the
+  // sizes that set the makespan.  The ordered core holds at most
+  // kOrdMaxFree free blocks: with larger meta_free it is not tried.
+  if (d->meta_free <= (int64_t)kOrdMaxFree) {
+    const std::vector<int32_t> longest = longest_heaps(off, 128, 1, kBudget, kHeavyCut);
+    const int64_t S2 = (int64_t)longest.size();
+    std::vector<hda_tuning> hc;
+    hda_tuning t = pick;
+    hc.push_back(t);
+    for (int64_t k : {int64_t(16), int64_t(64), int64_t(128)}) {
+      if (k > S2 && (k != 16 || S2 == 0)) continue;
+      t.heavy_heaps = (int32_t)std::min<int64_t>(k, S2);
+      t.heavy_kib = 64;
+      hc.push_back(t);
+    }
+    if (hc.size() > 1) {
+      hda_tuning pick2;
+      rc = time_candidates(d, off, arena, align, algo, longest, kHeavyCut, hc, s, &pick2);
+      if (rc != HDA_OK && rc != HDA_E_INVAL) return rc;
+      if (rc == HDA_OK) pick = pick2;
+    }
+  }
   hda_batch_desc dp = *d;
   dp.tuning = pick;
   return hda_replay_resolve(&dp, out);
