@@ -24,7 +24,8 @@ def build():
 def lib():
     global _lib
     if _lib is None:
-        L = ctypes.CDLL(build())
+        # HDA_EMU_LIB: a prebuilt emulator library (the sanitizer test's build)
+        L = ctypes.CDLL(os.environ.get("HDA_EMU_LIB") or build())
         vp = ctypes.c_void_p
         u32 = ctypes.c_uint32
         L.emu_replay.restype = ctypes.c_int
