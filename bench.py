@@ -30,8 +30,10 @@ sys.path.insert(0, ROOT)
 METRIC = ("alloc+free ops/s on 1 MI355X (batched vs per-heap replay); "
           "p50/p99 req latency")
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
-# the service's stated latency bound and the rate up to which it is stated
+# the service's stated latency bounds: p99 <= 200 us up to 1e7 requests/s,
+# <= 400 us at 2e7
 P99_BOUND_US, P99_BOUND_RATE = 200.0, 1e7
+P99_BOUND_TOP_US, P99_BOUND_TOP_RATE = 400.0, 2e7
 BYTES_PER_REQUEST = 16         # 8 B request read + 8 B result written
 # MI355X instruction issue: 256 CUs x 4 SIMDs, 2.4 GHz; a wave64 VALU
 # instruction takes 4 cycles on a 16-lane SIMD; one scalar unit per CU
@@ -448,21 +450,28 @@ def leg_serving(hda, rates, clients, seconds, bound_us, bound_rate):
     try:
         for rate in rates:
             rep, _ = srv.load(clients=clients, rate=rate, warmup_s=0.5, measure_s=seconds,
-                              threads=8)
+                              threads=max(1, min(16, host_cores())))
             if rep["errors"]:
                 raise RuntimeError(f"serving leg reported {rep['errors']} errors at {rate:g}/s")
             by_rate.append({"offered_rate": rate, "throughput": rep["throughput"],
                             "p50_us": rep["p50_us"], "p90_us": rep["p90_us"],
                             "p99_us": rep["p99_us"], "p999_us": rep["p999_us"],
                             "max_us": rep["max_us"], "completed": rep["completed"],
-                            "alloc_fail": rep["alloc_fail"], "window_s": rep["window_s"]})
+                            "alloc_fail": rep["alloc_fail"], "window_s": rep["window_s"],
+                            "components_us": {
+                                k: {"p50": rep[f"{k}_p50_us"], "p99": rep[f"{k}_p99_us"]}
+                                for k in ("host", "queue", "service", "transit")}})
             log(f"[bench] serving at {rate:.3g}/s: {rep['throughput']:.3g}/s, "
-                f"p50 {rep['p50_us']:.1f} us, p99 {rep['p99_us']:.1f} us")
+                f"p50 {rep['p50_us']:.1f} us, p99 {rep['p99_us']:.1f} us; p99 of host "
+                f"{rep['host_p99_us']:.1f}, queue {rep['queue_p99_us']:.1f}, service "
+                f"{rep['service_p99_us']:.1f}, transit {rep['transit_p99_us']:.1f} us")
     finally:
         srv.stop()
-    within = [r["p99_us"] <= bound_us for r in by_rate if r["offered_rate"] <= bound_rate]
+    within = [r["p99_us"] <= (bound_us if r["offered_rate"] <= bound_rate else P99_BOUND_TOP_US)
+              for r in by_rate if r["offered_rate"] <= P99_BOUND_TOP_RATE]
     return {"clients": clients, "unit": "requests/s",
-            "p99_bound_us": bound_us, "bound_rate": bound_rate,
+            "p99_bound_us": {f"{bound_rate:g}": bound_us,
+                             f"{P99_BOUND_TOP_RATE:g}": P99_BOUND_TOP_US},
             "within_bound": bool(within) and all(within), "by_rate": by_rate}
 
 

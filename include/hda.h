@@ -420,6 +420,13 @@ typedef struct hda_load_report {
   double window_s;                      /* measured window length           */
   double throughput;                    /* completions per second in window */
   double p50_us, p90_us, p99_us, p999_us, max_us, mean_us;
+  /* components of the measured latencies (p50 and p99 of each): waiting on
+   * the host before submission (the client's earlier request still in
+   * flight, or the load thread behind), queueing on the device (seen in the
+   * ring -> picked up by its wave), service on the device (picked up ->
+   * done), and the rest (ring transit both ways and harvesting) */
+  double host_p50_us, host_p99_us, queue_p50_us, queue_p99_us;
+  double service_p50_us, service_p99_us, transit_p50_us, transit_p99_us;
 } hda_load_report;
 
 int hda_serve_load(hda_server *s, const hda_load_config *cfg, hda_load_report *rep);

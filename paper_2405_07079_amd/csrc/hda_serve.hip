@@ -46,9 +46,14 @@ struct SubEntry {
   int64_t arg2;
   uint64_t seq;
 };
+// A completion: the result, the request's sequence number and three device
+// wall-clock readings -- when the wave first saw the request in its ring,
+// when it began serving it, and when it had served it.
 struct CplEntry {
   int64_t result;
   uint64_t seq;
+  uint64_t t_seen, t_pick, t_done;
+  uint64_t pad[3];
 };
 // Per wave: this header, then SubEntry[N], then CplEntry[N].
 struct RingHdr {
@@ -155,9 +160,12 @@ __global__ void __launch_bounds__(256) serve_kernel(ServeParams p) {
       __builtin_amdgcn_s_sleep(8);
       continue;
     }
-    // never more than a ring's worth per pass
+    // never more than a ring's worth per pass; every request of the pass was
+    // seen at `seen`
     const uint64_t end = tail - head > p.N ? head + p.N : tail;
+    const uint64_t seen = now;
     for (; head < end; ++head) {
+      const uint64_t t_pick = rdlane64(wall_clock64(), 0);
       // one 32-byte read of the entry: lanes 0..3 fetch its four words
       const uint64_t* e = reinterpret_cast<const uint64_t*>(&sub[head & mask]);
       const uint64_t word = e[lane_id() & 3u];
@@ -168,9 +176,13 @@ __global__ void __launch_bounds__(256) serve_kernel(ServeParams p) {
       const int64_t arg2 = (int64_t)rdlane64(word, 2);
       const uint64_t seq = rdlane64(word, 3);
       const int64_t r = serve_one(p, slot, op, arg, arg2);
+      const uint64_t t_done = rdlane64(wall_clock64(), 0);
       if (lane_id() == 0) {
         cpl[head & mask].result = r;
         cpl[head & mask].seq = seq;
+        cpl[head & mask].t_seen = seen;
+        cpl[head & mask].t_pick = t_pick;
+        cpl[head & mask].t_done = t_done;
         __hip_atomic_store(&hdr->cpl_tail, head + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
       }
     }
@@ -445,7 +457,7 @@ struct Client {
   bool busy = false;
   int op = 0;
   int64_t arg = 0, life = 0, issued_at = 0;
-  double arrival = 0;
+  double arrival = 0, submitted = 0;
   std::deque<double> waiting;
   std::vector<std::pair<int64_t, int64_t>> live;  // min-heap on expiry: (expiry, offset)
 };
@@ -455,10 +467,15 @@ struct LoadShared {
   hda_server* s;
   std::vector<Client>* clients;
   double t_warm, t_end;
+  double us_per_tick;   // device wall clock
 };
 
 struct ThreadOut {
   std::vector<float> lat_us;
+  // components of each measured latency: waiting on the host before the
+  // submission, device queueing (seen -> picked), device service (picked ->
+  // done), and the rest (ring transit both ways and the host's harvest)
+  std::vector<float> host_us, queue_us, service_us, transit_us;
   int64_t issued = 0, completed = 0, measured = 0, in_window = 0;
   int64_t alloc_ok = 0, alloc_fail = 0, frees = 0, errors = 0;
 };
@@ -494,6 +511,7 @@ void issue(LoadShared& L, Client& c, int32_t cid, double arrival,
   }
   c.issued_at = c.t++;
   c.arrival = arrival;
+  c.submitted = now_s();
   c.busy = true;
   uint64_t ticket;
   // a client has at most one request in flight and a ring serves fewer
@@ -523,6 +541,13 @@ void run_thread(LoadShared& L, int p, int T, ThreadOut& out) {
   double next = now_s();
   const double t_warm = L.t_warm, t_end = L.t_end;
   if (mine.empty()) return;
+  // room for every latency this thread can record (the offered rate's share
+  // over the window, with margin), so that no vector grows -- a reallocation
+  // would copy hundreds of megabytes while requests wait
+  const size_t expect = (size_t)(cfg.rate / T * (t_end - t_warm) * 1.3) + 4096;
+  for (std::vector<float>* v : {&out.lat_us, &out.host_us, &out.queue_us, &out.service_us,
+                                &out.transit_us})
+    v->reserve(expect);
   std::vector<uint64_t> seen(rings.size(), 0);
   for (size_t k = 0; k < rings.size(); ++k) {
     std::lock_guard<std::mutex> g(s->rs[rings[k]].mu);
@@ -563,6 +588,14 @@ void run_thread(LoadShared& L, int p, int T, ThreadOut& out) {
         ++out.completed;
         if (c.arrival >= t_warm && c.arrival < t_end) {
           out.lat_us.push_back((float)((tc - c.arrival) * 1e6));
+          const CplEntry& e = ce[q & (s->N - 1)];
+          const double q_us = (double)(e.t_pick - e.t_seen) * L.us_per_tick;
+          const double s_us = (double)(e.t_done - e.t_pick) * L.us_per_tick;
+          const double dev_us = (double)(e.t_done - e.t_seen) * L.us_per_tick;
+          out.host_us.push_back((float)((c.submitted - c.arrival) * 1e6));
+          out.queue_us.push_back((float)q_us);
+          out.service_us.push_back((float)s_us);
+          out.transit_us.push_back((float)((tc - c.submitted) * 1e6 - dev_us));
           ++out.measured;
         }
         if (tc >= t_warm && tc < t_end) ++out.in_window;
@@ -647,14 +680,23 @@ extern "C" int hda_serve_load(hda_server* s, const hda_load_config* cfg, hda_loa
     }
   }
   // the opens are queued ahead of every request on the same rings
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device) != hipSuccess ||
+      khz <= 0)
+    khz = 100000;
   const double t0 = now_s();
-  LoadShared L{cfg, s, &clients, t0 + cfg->warmup_s, t0 + cfg->warmup_s + cfg->measure_s};
+  LoadShared L{cfg, s, &clients, t0 + cfg->warmup_s, t0 + cfg->warmup_s + cfg->measure_s,
+               1e3 / (double)khz};
   std::vector<ThreadOut> outs(T);
   std::vector<std::thread> th;
   for (int p = 0; p < T; ++p) th.emplace_back(run_thread, std::ref(L), p, T, std::ref(outs[p]));
   for (auto& t : th) t.join();
-  std::vector<float> lat;
+  std::vector<float> lat, hq, dq, ds, tr;
   for (auto& o : outs) {
+    hq.insert(hq.end(), o.host_us.begin(), o.host_us.end());
+    dq.insert(dq.end(), o.queue_us.begin(), o.queue_us.end());
+    ds.insert(ds.end(), o.service_us.begin(), o.service_us.end());
+    tr.insert(tr.end(), o.transit_us.begin(), o.transit_us.end());
     rep->issued += o.issued; rep->completed += o.completed; rep->measured += o.measured;
     rep->alloc_ok += o.alloc_ok; rep->alloc_fail += o.alloc_fail; rep->frees += o.frees;
     rep->errors += o.errors;
@@ -663,12 +705,18 @@ extern "C" int hda_serve_load(hda_server* s, const hda_load_config* cfg, hda_loa
   }
   rep->window_s = cfg->measure_s;
   rep->throughput /= cfg->measure_s;
+  auto pct = [](std::vector<float>& v, double f) {
+    if (v.empty()) return 0.0;
+    size_t k = (size_t)std::min<double>(v.size() - 1, std::floor(f * (v.size() - 1) + 0.5));
+    std::nth_element(v.begin(), v.begin() + k, v.end());
+    return (double)v[k];
+  };
+  rep->host_p50_us = pct(hq, 0.5); rep->host_p99_us = pct(hq, 0.99);
+  rep->queue_p50_us = pct(dq, 0.5); rep->queue_p99_us = pct(dq, 0.99);
+  rep->service_p50_us = pct(ds, 0.5); rep->service_p99_us = pct(ds, 0.99);
+  rep->transit_p50_us = pct(tr, 0.5); rep->transit_p99_us = pct(tr, 0.99);
   if (!lat.empty()) {
-    auto q = [&](double f) {
-      size_t k = (size_t)std::min<double>(lat.size() - 1, std::floor(f * (lat.size() - 1) + 0.5));
-      std::nth_element(lat.begin(), lat.begin() + k, lat.end());
-      return (double)lat[k];
-    };
+    auto q = [&](double f) { return pct(lat, f); };
     double sum = 0;
     for (float v : lat) sum += v;
     rep->mean_us = sum / lat.size();

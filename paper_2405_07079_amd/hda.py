@@ -92,7 +92,11 @@ class hda_load_report(ctypes.Structure):
                 ("throughput", ctypes.c_double), ("p50_us", ctypes.c_double),
                 ("p90_us", ctypes.c_double), ("p99_us", ctypes.c_double),
                 ("p999_us", ctypes.c_double), ("max_us", ctypes.c_double),
-                ("mean_us", ctypes.c_double)]
+                ("mean_us", ctypes.c_double),
+                ("host_p50_us", ctypes.c_double), ("host_p99_us", ctypes.c_double),
+                ("queue_p50_us", ctypes.c_double), ("queue_p99_us", ctypes.c_double),
+                ("service_p50_us", ctypes.c_double), ("service_p99_us", ctypes.c_double),
+                ("transit_p50_us", ctypes.c_double), ("transit_p99_us", ctypes.c_double)]
 
 
 HDA_OP_ALLOC, HDA_OP_FREE = 1, 2
@@ -213,7 +217,11 @@ def torch_available() -> bool:
 
 def use_torch_allocator() -> None:
     """Route the library's own device buffers through torch's caching
-    allocator (done when the library is loaded on a machine with a GPU)."""
+    allocator (done when the library is loaded on a machine with a GPU).
+    torch's device state is set up first: it cannot be brought up from
+    inside the library's callback."""
+    import torch
+    torch.cuda.init()
     _check(lib().hda_set_device_allocator(*_TORCH_ALLOCATOR, None), "hda_set_device_allocator")
 
 

@@ -123,7 +123,8 @@ def test_service_at_full_load():
     say("case: service, 100,000 clients, 1e7 requests/s offered, 1 s measured")
     s = hda.Server(max_heaps=100_016, max_seconds=300)
     try:
-        rep, _ = s.load(clients=100_000, rate=1e7, warmup_s=0.3, measure_s=1.0, threads=8)
+        rep, _ = s.load(clients=100_000, rate=1e7, warmup_s=0.3, measure_s=1.0,
+                        threads=host_threads())
     finally:
         s.stop()
     say("report", rep)
