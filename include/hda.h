@@ -411,7 +411,17 @@ typedef struct hda_load_config {
   double lifetime_mean;
   uint64_t seed;
   int32_t close_heaps;    /* 1: close every client heap at the end          */
-  int32_t reserved;
+  int32_t session_len;    /* 0: every client holds one heap for the whole
+                             run (all admitted before it starts; a refused
+                             admission ends the call with its error).  n > 0:
+                             clients work in sessions of n requests -- a
+                             session opens a fresh heap of the client's arena
+                             when the metadata budget admits it (until then
+                             the client's arrivals wait, and their wait counts
+                             in their latency) and closes it after its n-th
+                             request, returning its budget; a logged client's
+                             log then has a (0, arena, align) row at the start
+                             of each session                                */
 } hda_load_config;
 
 typedef struct hda_load_report {
@@ -427,9 +437,18 @@ typedef struct hda_load_report {
    * done), and the rest (ring transit both ways and harvesting) */
   double host_p50_us, host_p99_us, queue_p50_us, queue_p99_us;
   double service_p50_us, service_p99_us, transit_p50_us, transit_p99_us;
+  int64_t sessions;         /* sessions ended (heaps closed) during the run  */
+  int64_t admission_waits;  /* times a client with requests waited for
+                               admission                                     */
+  int64_t max_open;         /* most heaps open at once                       */
+  int64_t slot_bytes;       /* metadata bytes one open heap holds             */
 } hda_load_report;
 
 int hda_serve_load(hda_server *s, const hda_load_config *cfg, hda_load_report *rep);
+
+/* Bytes of device metadata one admitted heap holds under `cfg` (the unit of
+ * the metadata budget), or HDA_E_INVAL. */
+int64_t hda_serve_slot_bytes(const hda_serve_config *cfg);
 
 /* Static description of an error code. */
 const char *hda_strerror(int code);

@@ -451,13 +451,15 @@ struct Rng {  // SplitMix64 (Steele, Lea, Flood 2014)
 };
 
 struct Client {
-  int32_t heap = -1;
+  int32_t heap = -1;                   // -1: no heap (waiting for admission)
   Rng rng{0};
   int64_t t = 0;                       // requests issued
   bool busy = false;
   int op = 0;
   int64_t arg = 0, life = 0, issued_at = 0;
   double arrival = 0, submitted = 0;
+  uint64_t arena = 0;                  // the client's arena bytes
+  int64_t session_left = 0;            // requests left in this session (sessions)
   std::deque<double> waiting;
   std::vector<std::pair<int64_t, int64_t>> live;  // min-heap on expiry: (expiry, offset)
 };
@@ -468,6 +470,7 @@ struct LoadShared {
   std::vector<Client>* clients;
   double t_warm, t_end;
   double us_per_tick;   // device wall clock
+  std::atomic<int64_t> open_now{0}, open_max{0};
 };
 
 struct ThreadOut {
@@ -478,6 +481,7 @@ struct ThreadOut {
   std::vector<float> host_us, queue_us, service_us, transit_us;
   int64_t issued = 0, completed = 0, measured = 0, in_window = 0;
   int64_t alloc_ok = 0, alloc_fail = 0, frees = 0, errors = 0;
+  int64_t sessions = 0, admission_waits = 0;
 };
 
 uint64_t log_uniform(Rng& r, double lo, double hi) {
@@ -485,8 +489,82 @@ uint64_t log_uniform(Rng& r, double lo, double hi) {
   return (uint64_t)std::min(std::max(v, lo), hi);
 }
 
-void issue(LoadShared& L, Client& c, int32_t cid, double arrival,
-           std::vector<int32_t>& owner_of, int ring_base) {
+// Enqueue on a ring that only this load thread consumes.  Each client has at
+// most an initialisation and one request or close in flight, and a ring
+// serves fewer than half as many clients as it has entries, so a full ring
+// frees up as the device works; a ring still full after 10 s (the service
+// gone) gives kFullRing, which the caller counts as an error.
+uint64_t push_load(hda_server* s, int32_t slot, int32_t op, int64_t arg, int64_t arg2) {
+  uint64_t t = s->push(slot, op, arg, arg2, false);
+  const double give_up = now_s() + 10.0;
+  while (t == hda_server::kFullRing && now_s() < give_up) {
+    std::this_thread::yield();
+    t = s->push(slot, op, arg, arg2, false);
+  }
+  return t;
+}
+
+// owner marks in a ring position: >= 0 a client's request, -1 nothing of
+// the load's, <= -2 the close of client -(mark + 2)'s heap
+constexpr int32_t kNoOwner = -1;
+int32_t close_mark(int32_t cid) { return -2 - cid; }
+
+void note_open(LoadShared& L, int64_t d) {
+  const int64_t n = L.open_now.fetch_add(d) + d;
+  int64_t m = L.open_max.load();
+  while (n > m && !L.open_max.compare_exchange_weak(m, n)) {
+  }
+}
+
+// Admit a heap for client c whose ring belongs to load thread p of T (so the
+// thread that consumes that ring also owns the client), within the metadata
+// budget: the slot closest to the end of the free list among those of the
+// thread's rings.  Queues the heap's initialisation.  False when the budget
+// or the thread's slots are used up.
+bool open_for_thread(LoadShared& L, Client& c, int32_t cid, int p, int T) {
+  hda_server* s = L.s;
+  const hda_load_config& cfg = *L.cfg;
+  int32_t slot = -1;
+  {
+    std::lock_guard<std::mutex> g(s->slots_mu);
+    if (s->held + (int64_t)s->slot_bytes > s->budget) return false;
+    for (size_t k = s->free_slots.size(); k-- > 0;) {
+      const int32_t cand = s->free_slots[k];
+      if ((cand % s->G) % T == p) {
+        slot = cand;
+        s->free_slots.erase(s->free_slots.begin() + (ptrdiff_t)k);
+        break;
+      }
+    }
+    if (slot < 0) return false;
+    s->held += (int64_t)s->slot_bytes;
+  }
+  const int64_t arg2 = ((int64_t)cfg.algo << 8) | (int64_t)__builtin_ctzll(cfg.align);
+  if (push_load(s, slot, kSrvInit, (int64_t)c.arena, arg2) == hda_server::kFullRing) {
+    std::lock_guard<std::mutex> g(s->slots_mu);
+    s->free_slots.push_back(slot);
+    s->held -= (int64_t)s->slot_bytes;
+    return false;
+  }
+  c.heap = slot;
+  c.session_left = cfg.session_len;
+  c.live.clear();
+  note_open(L, 1);
+  if (cid < cfg.log_clients && cfg.log && cfg.log_len) {  // a session starts: (0, arena, align)
+    const int64_t n = cfg.log_len[cid];
+    if (n < cfg.log_cap) {
+      int64_t* e = cfg.log + ((int64_t)cid * cfg.log_cap + n) * 3;
+      e[0] = 0; e[1] = (int64_t)c.arena; e[2] = (int64_t)cfg.align;
+      cfg.log_len[cid] = n + 1;
+    }
+  }
+  return true;
+}
+
+// Issue client c's next request (arrived at `arrival`); false if it could
+// not be enqueued (the client is then left idle).
+bool issue(LoadShared& L, Client& c, int32_t cid, double arrival,
+           std::vector<int32_t>& owner_of) {
   const hda_load_config& cfg = *L.cfg;
   auto cmp = [](const std::pair<int64_t, int64_t>& a, const std::pair<int64_t, int64_t>& b) {
     return a.first > b.first;
@@ -513,12 +591,11 @@ void issue(LoadShared& L, Client& c, int32_t cid, double arrival,
   c.arrival = arrival;
   c.submitted = now_s();
   c.busy = true;
-  uint64_t ticket;
-  // a client has at most one request in flight and a ring serves fewer
-  // clients than it has entries, so the ring cannot stay full; spin if it is
-  while ((ticket = L.s->push(c.heap, c.op, c.arg, 0, false)) == hda_server::kFullRing)
-    std::this_thread::yield();
-  owner_of[((ticket >> 40) - ring_base) * L.s->N + (ticket & (L.s->N - 1))] = cid;
+  if (cfg.session_len > 0) --c.session_left;
+  const uint64_t ticket = push_load(L.s, c.heap, c.op, c.arg, 0);
+  if (ticket == hda_server::kFullRing) return false;
+  owner_of[(ticket >> 40) * L.s->N + (ticket & (L.s->N - 1))] = cid;
+  return true;
 }
 
 void run_thread(LoadShared& L, int p, int T, ThreadOut& out) {
@@ -526,16 +603,20 @@ void run_thread(LoadShared& L, int p, int T, ThreadOut& out) {
   const hda_load_config& cfg = *L.cfg;
   std::vector<Client>& cl = *L.clients;
   // this thread's rings are r = p, p+T, ...; its clients are those whose heap
-  // lives on them.  Only this thread submits to or consumes those rings.
+  // lives on them (and, with sessions, those waiting for admission whose
+  // number is p mod T).  Only this thread submits to or consumes those rings.
   std::vector<int> rings;
   for (int r = p; r < s->G; r += T) rings.push_back(r);
   std::vector<int32_t> mine;
-  for (int32_t c = 0; c < (int32_t)cl.size(); ++c)
-    if ((cl[c].heap % s->G) % T == p) mine.push_back(c);
-  // owner_of: completion slot -> client, for this thread's rings (indexed by
-  // ring position in `rings`)
-  const int ring_base = 0;
-  std::vector<int32_t> owner(s->G * (size_t)s->N, -1);
+  std::deque<int32_t> pending;  // clients waiting for admission, first come first
+  for (int32_t c = 0; c < (int32_t)cl.size(); ++c) {
+    const bool ours = cl[c].heap >= 0 ? (cl[c].heap % s->G) % T == p : c % T == p;
+    if (!ours) continue;
+    mine.push_back(c);
+    if (cl[c].heap < 0) pending.push_back(c);
+  }
+  // owner_of: completion slot -> client (or a close mark), for every ring
+  std::vector<int32_t> owner(s->G * (size_t)s->N, kNoOwner);
   Rng arr{cfg.seed * 0x9e3779b97f4a7c15ull + (uint64_t)p * 7919 + 1};
   const double rate = cfg.rate / T;
   double next = now_s();
@@ -556,19 +637,43 @@ void run_thread(LoadShared& L, int p, int T, ThreadOut& out) {
   auto cmp = [](const std::pair<int64_t, int64_t>& a, const std::pair<int64_t, int64_t>& b) {
     return a.first > b.first;
   };
-  int64_t busy = 0;
+  int64_t busy = 0;      // requests and closes in flight
   for (;;) {
     const double now = now_s();
     bool did = false;
+    // admit waiting clients while the budget allows, in arrival order
+    while (!pending.empty()) {
+      const int32_t cid = pending.front();
+      Client& c = cl[cid];
+      if (!open_for_thread(L, c, cid, p, T)) break;
+      pending.pop_front();
+      did = true;
+      if (!c.waiting.empty()) {
+        const double a = c.waiting.front();
+        c.waiting.pop_front();
+        if (issue(L, c, cid, a, owner)) {
+          ++busy;
+          ++out.issued;
+        } else {
+          c.busy = false;
+          ++out.errors;
+        }
+      }
+    }
     while (next <= now && next < t_end) {
       const int32_t cid = mine[(size_t)(arr.uniform() * mine.size()) % mine.size()];
       Client& c = cl[cid];
-      if (c.busy) {
+      if (c.busy || c.heap < 0) {
+        if (c.heap < 0 && !c.busy && c.waiting.empty()) ++out.admission_waits;
         c.waiting.push_back(next);
       } else {
-        issue(L, c, cid, next, owner, ring_base);
-        ++busy;
-        ++out.issued;
+        if (issue(L, c, cid, next, owner)) {
+          ++busy;
+          ++out.issued;
+        } else {
+          c.busy = false;
+          ++out.errors;
+        }
       }
       next += -std::log(1.0 - arr.uniform()) / rate;
       did = true;
@@ -581,9 +686,29 @@ void run_thread(LoadShared& L, int p, int T, ThreadOut& out) {
       CplEntry* ce = s->cpl(r);
       for (uint64_t q = seen[k]; q < ct; ++q) {
         const int64_t res = ce[q & (s->N - 1)].result;
-        const int32_t cid = owner[(size_t)r * s->N + (q & (s->N - 1))];
-        if (cid < 0) continue;  // not a load request (e.g. an open)
-        owner[(size_t)r * s->N + (q & (s->N - 1))] = -1;
+        const int32_t who = owner[(size_t)r * s->N + (q & (s->N - 1))];
+        owner[(size_t)r * s->N + (q & (s->N - 1))] = kNoOwner;
+        if (who == kNoOwner) continue;  // not a load request (e.g. an open)
+        if (who <= -2) {
+          // a session's heap is closed on the device: its slot and budget
+          // return, and the client waits for admission again
+          const int32_t cid = -(who + 2);
+          Client& c = cl[cid];
+          note_open(L, -1);  // counted closed before its budget can be reused
+          {
+            std::lock_guard<std::mutex> g(s->slots_mu);
+            s->free_slots.push_back(c.heap);
+            s->held -= (int64_t)s->slot_bytes;
+          }
+          c.heap = -1;
+          c.busy = false;
+          --busy;
+          ++out.sessions;
+          if (!c.waiting.empty()) ++out.admission_waits;
+          pending.push_back(cid);
+          continue;
+        }
+        const int32_t cid = who;
         Client& c = cl[cid];
         ++out.completed;
         if (c.arrival >= t_warm && c.arrival < t_end) {
@@ -623,12 +748,26 @@ void run_thread(LoadShared& L, int p, int T, ThreadOut& out) {
         }
         c.busy = false;
         --busy;
-        if (!c.waiting.empty()) {
+        if (cfg.session_len > 0 && c.session_left <= 0) {
+          // the session ends: close its heap (completion handled above)
+          const uint64_t t = push_load(s, c.heap, kSrvClose, 0, 0);
+          if (t == hda_server::kFullRing) {
+            ++out.errors;
+          } else {
+            owner[(t >> 40) * s->N + (t & (s->N - 1))] = close_mark(cid);
+            c.busy = true;
+            ++busy;
+          }
+        } else if (!c.waiting.empty()) {
           const double a = c.waiting.front();
           c.waiting.pop_front();
-          issue(L, c, cid, a, owner, ring_base);
-          ++busy;
-          ++out.issued;
+          if (issue(L, c, cid, a, owner)) {
+            ++busy;
+            ++out.issued;
+          } else {
+            c.busy = false;
+            ++out.errors;
+          }
         }
       }
       // the ring's entries up to ct are consumed and free for reuse
@@ -656,23 +795,37 @@ extern "C" int hda_serve_load(hda_server* s, const hda_load_config* cfg, hda_loa
   if (!s || !cfg || !rep || cfg->clients <= 0 || cfg->rate <= 0 || cfg->measure_s <= 0 ||
       cfg->warmup_s < 0 || cfg->pow2_lo > cfg->pow2_hi || cfg->size_lo == 0 ||
       cfg->size_lo > cfg->size_hi || cfg->arena_lo == 0 || cfg->arena_lo > cfg->arena_hi ||
-      cfg->lifetime_mean <= 0 || (cfg->log_clients > 0 && (!cfg->log || !cfg->log_len)))
+      cfg->lifetime_mean <= 0 || cfg->session_len < 0 ||
+      (cfg->log_clients > 0 && (!cfg->log || !cfg->log_len)))
     return HDA_E_INVAL;
   std::memset(rep, 0, sizeof(*rep));
   int T = cfg->threads > 0 ? cfg->threads : 4;
   while (T > 1 && s->G % T) --T;
   std::vector<Client> clients(cfg->clients);
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device) != hipSuccess ||
+      khz <= 0)
+    khz = 100000;
+  LoadShared L;
+  L.cfg = cfg;
+  L.s = s;
+  L.clients = &clients;
+  L.us_per_tick = 1e3 / (double)khz;
   for (int32_t c = 0; c < cfg->clients; ++c) {
     Client& k = clients[c];
     k.rng.x = cfg->seed * 0x2545f4914f6cdd1dull + (uint64_t)c * 0x9e3779b97f4a7c15ull;
     uint64_t a = log_uniform(k.rng, (double)cfg->arena_lo, (double)cfg->arena_hi);
     a = a / cfg->align * cfg->align;
     if (a == 0) a = cfg->align;
+    k.arena = a;
+    if (c < cfg->log_clients) cfg->log_len[c] = 0;
+    if (cfg->session_len > 0) continue;  // sessions: admitted by the load threads
     const int rc = hda_serve_open(s, a, cfg->align, cfg->algo, &k.heap);
     if (rc != HDA_OK) {
       for (int32_t j = 0; j < c; ++j) hda_serve_close(s, clients[j].heap);
       return rc;
     }
+    note_open(L, 1);
     if (c < cfg->log_clients) {  // row 0 of a client's log: (0, arena, align)
       int64_t* e = cfg->log + (int64_t)c * cfg->log_cap * 3;
       e[0] = 0; e[1] = (int64_t)a; e[2] = (int64_t)cfg->align;
@@ -680,13 +833,9 @@ extern "C" int hda_serve_load(hda_server* s, const hda_load_config* cfg, hda_loa
     }
   }
   // the opens are queued ahead of every request on the same rings
-  int khz = 0;
-  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device) != hipSuccess ||
-      khz <= 0)
-    khz = 100000;
   const double t0 = now_s();
-  LoadShared L{cfg, s, &clients, t0 + cfg->warmup_s, t0 + cfg->warmup_s + cfg->measure_s,
-               1e3 / (double)khz};
+  L.t_warm = t0 + cfg->warmup_s;
+  L.t_end = t0 + cfg->warmup_s + cfg->measure_s;
   std::vector<ThreadOut> outs(T);
   std::vector<std::thread> th;
   for (int p = 0; p < T; ++p) th.emplace_back(run_thread, std::ref(L), p, T, std::ref(outs[p]));
@@ -700,9 +849,13 @@ extern "C" int hda_serve_load(hda_server* s, const hda_load_config* cfg, hda_loa
     rep->issued += o.issued; rep->completed += o.completed; rep->measured += o.measured;
     rep->alloc_ok += o.alloc_ok; rep->alloc_fail += o.alloc_fail; rep->frees += o.frees;
     rep->errors += o.errors;
+    rep->sessions += o.sessions;
+    rep->admission_waits += o.admission_waits;
     rep->throughput += (double)o.in_window;
     lat.insert(lat.end(), o.lat_us.begin(), o.lat_us.end());
   }
+  rep->max_open = L.open_max.load();
+  rep->slot_bytes = (int64_t)s->slot_bytes;
   rep->window_s = cfg->measure_s;
   rep->throughput /= cfg->measure_s;
   auto pct = [](std::vector<float>& v, double f) {
@@ -727,6 +880,16 @@ extern "C" int hda_serve_load(hda_server* s, const hda_load_config* cfg, hda_loa
     rep->max_us = *std::max_element(lat.begin(), lat.end());
   }
   if (cfg->close_heaps)
-    for (auto& k : clients) hda_serve_close(s, k.heap);
+    for (auto& k : clients)
+      if (k.heap >= 0) hda_serve_close(s, k.heap);
   return HDA_OK;
+}
+
+// Bytes of device metadata one admitted heap holds under `cfg` (what the
+// metadata budget is counted in).
+extern "C" int64_t hda_serve_slot_bytes(const hda_serve_config* cfg) {
+  if (!cfg || cfg->slot_free < 0 || cfg->slot_live < 0) return HDA_E_INVAL;
+  const uint32_t cf = (uint32_t)(((cfg->slot_free ? cfg->slot_free : 512) + 63) / 64 * 64);
+  const uint32_t cl = (uint32_t)(((cfg->slot_live ? cfg->slot_live : 512) + 63) / 64 * 64);
+  return (int64_t)((heap_bytes(cf, cl) + 255) / 256 * 256);
 }

@@ -81,7 +81,7 @@ class hda_load_config(ctypes.Structure):
                 ("pow2_hi", ctypes.c_int32), ("size_lo", ctypes.c_uint64),
                 ("size_hi", ctypes.c_uint64), ("lifetime_mean", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("close_heaps", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("session_len", ctypes.c_int32)]
 
 
 class hda_load_report(ctypes.Structure):
@@ -96,7 +96,9 @@ class hda_load_report(ctypes.Structure):
                 ("host_p50_us", ctypes.c_double), ("host_p99_us", ctypes.c_double),
                 ("queue_p50_us", ctypes.c_double), ("queue_p99_us", ctypes.c_double),
                 ("service_p50_us", ctypes.c_double), ("service_p99_us", ctypes.c_double),
-                ("transit_p50_us", ctypes.c_double), ("transit_p99_us", ctypes.c_double)]
+                ("transit_p50_us", ctypes.c_double), ("transit_p99_us", ctypes.c_double),
+                ("sessions", ctypes.c_int64), ("admission_waits", ctypes.c_int64),
+                ("max_open", ctypes.c_int64), ("slot_bytes", ctypes.c_int64)]
 
 
 HDA_OP_ALLOC, HDA_OP_FREE = 1, 2
@@ -129,7 +131,8 @@ EXPORTS = ["hda_set_device_allocator", "hda_heap_load",
            "hda_heap_create", "hda_heap_destroy", "hda_alloc",
            "hda_free", "hda_free_partial", "hda_heap_state", "hda_set_meta_budget", "hda_strerror",
            "hda_serve_start", "hda_serve_open", "hda_serve_submit", "hda_serve_poll",
-           "hda_serve_wait", "hda_serve_close", "hda_serve_stop", "hda_serve_load"]
+           "hda_serve_wait", "hda_serve_close", "hda_serve_stop", "hda_serve_load",
+           "hda_serve_slot_bytes"]
 
 
 def lib():
@@ -201,6 +204,8 @@ def lib():
             fn = getattr(L, name)
             fn.restype = ctypes.c_int
             fn.argtypes = args
+        L.hda_serve_slot_bytes.restype = ctypes.c_int64
+        L.hda_serve_slot_bytes.argtypes = [ctypes.POINTER(hda_serve_config)]
         _lib = L
         if torch_available():
             use_torch_allocator()
@@ -532,6 +537,15 @@ class Server:
         _check(lib().hda_serve_start(ctypes.byref(cfg), ctypes.byref(h)), "hda_serve_start")
         self._s = h
 
+    @staticmethod
+    def slot_bytes(slot_free: int = 0, slot_live: int = 0) -> int:
+        """Metadata bytes one admitted heap holds (the budget's unit)."""
+        cfg = hda_serve_config(0, 1, int(slot_free), int(slot_live), 0, 0, 0, 0.0)
+        n = lib().hda_serve_slot_bytes(ctypes.byref(cfg))
+        if n < 0:
+            raise HdaError(int(n), "hda_serve_slot_bytes")
+        return int(n)
+
     def open(self, arena: int, align: int, algo: int) -> int:
         heap = ctypes.c_int32()
         _check(lib().hda_serve_open(self._s, int(arena), int(align), int(algo),
@@ -568,9 +582,10 @@ class Server:
              algo: int = SEG_FIT, threads: int = 0, log_clients: int = 0, log_cap: int = 0,
              arena=(64 << 20, 4 << 30), align: int = 512, p_pow2: float = 0.7,
              pow2=(9, 28), size=(512, 256 << 20), lifetime_mean: float = 500.0,
-             seed: int = 4, close_heaps: bool = True):
+             seed: int = 4, close_heaps: bool = True, session_len: int = 0):
         """Run the open-loop client load; returns (report dict, logs or None).
-        logs[c] is an array of (op, arg, result) rows for client c."""
+        logs[c] is an array of (op, arg, result) rows for client c, with a
+        (0, arena, align) row where each of its heaps (sessions) begins."""
         log = log_len = None
         if log_clients:
             log = np.zeros((log_clients, log_cap, 3), np.int64)
@@ -581,7 +596,8 @@ class Server:
             None if log_len is None else log_len.ctypes.data,
             int(arena[0]), int(arena[1]), int(align), float(rate), float(warmup_s),
             float(measure_s), float(p_pow2), int(pow2[0]), int(pow2[1]), int(size[0]),
-            int(size[1]), float(lifetime_mean), int(seed), int(bool(close_heaps)), 0)
+            int(size[1]), float(lifetime_mean), int(seed), int(bool(close_heaps)),
+            int(session_len))
         rep = hda_load_report()
         _check(lib().hda_serve_load(self._s, ctypes.byref(cfg), ctypes.byref(rep)),
                "hda_serve_load")

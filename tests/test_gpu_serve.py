@@ -107,6 +107,55 @@ def test_admission_by_metadata_budget():
         s.stop()
 
 
+def split_sessions(log):
+    """A logged client's sessions: lists of rows, each starting with its
+    (0, arena, align) row."""
+    starts = [i for i in range(len(log)) if log[i, 0] == 0] + [len(log)]
+    return [log[a:b] for a, b in zip(starts, starts[1:])]
+
+
+def test_admission_under_load_with_sessions():
+    """2,000 clients under open-loop load with a metadata budget of 200 heaps
+    (10 % of what holding every client's heap would need).  Clients work in
+    sessions of 40 requests: a session opens a heap when the budget admits
+    it and closes it at the end, so closed sessions make room for waiting
+    clients while the others' requests are on the GPU.  Every logged
+    session's results equal an oracle replay of that session, and one of
+    them replayed alone gives the same results as in the mix."""
+    slot = hda.Server.slot_bytes(64, 64)
+    clients, admitted = 2000, 200
+    s = hda.Server(max_heaps=clients, waves=32, slot_free=64, slot_live=64, max_seconds=120,
+                   meta_budget=admitted * slot)
+    try:
+        say(f"case: admission under load, {clients} clients, budget {admitted} heaps")
+        rep, logs = s.load(clients=clients, rate=200_000, warmup_s=0.2, measure_s=1.0,
+                           threads=4, session_len=40, log_clients=60, log_cap=8192,
+                           arena=(1 << 20, 64 << 20), size=(512, 1 << 20), pow2=(9, 20),
+                           lifetime_mean=15)
+        say("report", rep)
+        assert rep["errors"] == 0 and rep["completed"] == rep["issued"] > 100_000
+        assert rep["slot_bytes"] == slot
+        assert admitted // 2 < rep["max_open"] <= admitted
+        assert rep["sessions"] > clients          # budget freed and re-used
+        assert rep["admission_waits"] > 0
+        n_sessions = 0
+        for c, log in enumerate(logs):
+            for sess in split_sessions(log):
+                if len(sess) > 1:
+                    assert np.array_equal(sess[1:, 2], replay_log(sess)), f"client {c}"
+                    n_sessions += 1
+        assert n_sessions > len(logs)
+        # one session alone on a fresh heap: the same results as in the mix
+        sess = max((x for lg in logs for x in split_sessions(lg)), key=len)
+        _, arena, align = (int(x) for x in sess[0])
+        h = s.open(arena, align, hda.SEG_FIT)
+        alone = [s.wait(s.submit(h, int(op), int(arg))) for op, arg, _ in sess[1:]]
+        assert np.array_equal(np.array(alone), sess[1:, 2])
+        s.close_heap(h)
+    finally:
+        s.stop()
+
+
 def test_watchdog_ends_the_kernel():
     say("case: watchdog")
     s = hda.Server(max_heaps=4, waves=2, max_seconds=1.0)
