@@ -7,7 +7,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhda.so")
 SOURCES = ["hda_replay.hip", "hda_heap.hip", "hda_serve.hip", "hda_bitmap.hip"]
-HEADERS = ["hda_wave.h", "hda_core.h", "hda_lean.h", "hda_bitmap.h", "hda_replay_body.h",
+HEADERS = ["hda_wave.h", "hda_core.h", "hda_lean.h", "hda_ordered.h", "hda_bitmap.h", "hda_replay_body.h",
            "hda_heap_dev.h", "hda_mem.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
