@@ -119,16 +119,23 @@ struct BitHeap {
   HDA_GLOBAL uint64_t* bits;   // nw words: bit i of word w = granule 64 w + i free
   HDA_GLOBAL uint64_t* nodes;  // nn node summaries, node n = words 64 n .. 64 n + 63
   HDA_GLOBAL Ent* live;        // capL entries
+  // the first kn node summaries and the first kl live entries are kept in the
+  // wave's LDS instead (the device-memory places of those stay unused)
+  HDA_LDS uint64_t* lnodes;
+  HDA_LDS Ent* llive;
+  uint32_t kn, kl;
   int64_t arena;
   uint32_t shift, ag, nw, nn;
   uint32_t L, rover, capL;
   uint32_t cn;  // node whose words the last word step or mark left in cw, or kNone
   uint64_t cw;  // that node's word of this lane (no mask applied)
 
-  __device__ __forceinline__ BitHeap(uint64_t* b, uint64_t* nd, Ent* lv, const HeapRegs& h,
-                                     uint32_t cap_live)
+  __device__ __forceinline__ BitHeap(uint64_t* b, uint64_t* nd, Ent* lv, HDA_LDS uint64_t* lnd,
+                                     uint32_t n_lds_nodes, HDA_LDS Ent* llv, uint32_t n_lds_live,
+                                     const HeapRegs& h, uint32_t cap_live)
       : bits((HDA_GLOBAL uint64_t*)b), nodes((HDA_GLOBAL uint64_t*)nd),
-        live((HDA_GLOBAL Ent*)lv), arena(h.arena), shift(h.shift), ag(h.ag),
+        live((HDA_GLOBAL Ent*)lv), lnodes(lnd), llive(llv), kn(n_lds_nodes), kl(n_lds_live),
+        arena(h.arena), shift(h.shift), ag(h.ag),
         nw((uint32_t)(((uint64_t)h.ag + 63u) >> 6)),  // ag may be 2^32 - 1
         nn((uint32_t)(((uint64_t)h.ag + 4095u) >> 12)), L(0), rover(0),
         capL(cap_live), cn(kNone), cw(0) {}
@@ -139,8 +146,24 @@ struct BitHeap {
     return wi < nw ? v : 0ull;
   }
   __device__ __forceinline__ uint64_t load_node(uint32_t ni) const {
-    const uint64_t v = nodes[ni < nn ? ni : nn - 1u];
+    const uint32_t i = ni < nn ? ni : nn - 1u;
+    wave_sync();
+    const uint64_t v = i < kn ? lnodes[i] : nodes[i];
     return ni < nn ? v : 0ull;
+  }
+  __device__ __forceinline__ void put_node(uint32_t n, uint64_t v) const {
+    wave_sync();
+    if (n < kn) lnodes[n] = v;  // every lane, same value
+    else if (lane_id() == 0u) nodes[n] = v;
+  }
+  // live entry i (wave-uniform), as the same value in every lane
+  __device__ __forceinline__ Ent live_get(uint32_t i) const {
+    wave_sync();
+    return i < kl ? llive[i] : live[i];
+  }
+  __device__ __forceinline__ void live_put(uint32_t i, Ent e) const {
+    wave_sync();
+    if (i < kl) llive[i] = e; else live[i] = e;  // every lane, same value
   }
 
   // Alg. 6: every granule free.
@@ -155,7 +178,11 @@ struct BitHeap {
       const uint32_t rest = ag - kNodeGranules * (ni < nn ? ni : 0u);
       const uint32_t g = rest < kNodeGranules ? rest : kNodeGranules;  // one run [0, g)
       const uint32_t top = g == kNodeGranules ? g : 0u;
-      if (ni < nn) nodes[ni] = (uint64_t)g | ((uint64_t)top << 16) | ((uint64_t)g << 32);
+      const uint64_t v = (uint64_t)g | ((uint64_t)top << 16) | ((uint64_t)g << 32);
+      wave_sync();
+      if (ni < nn) {
+        if (ni < kn) lnodes[ni] = v; else nodes[ni] = v;
+      }
     }
     L = 0;
     rover = 0;
@@ -265,7 +292,7 @@ struct BitHeap {
       cn = n;
       cw = nv;
       const uint64_t sum = node_summary(nv);
-      if (lane_id() == 0u) nodes[n] = sum;
+      put_node(n, sum);
     }
   }
 
@@ -278,7 +305,7 @@ struct BitHeap {
     if (p == kNone) return kFail;
     if (L >= capL) return kENoMeta;
     mark(p, sg, false);
-    live[L] = mk_ent(p, sg);  // every lane, same value
+    live_put(L, mk_ent(p, sg));
     ++L;
     rover = p + sg;
     return (int64_t)((uint64_t)p << shift);
@@ -290,15 +317,16 @@ struct BitHeap {
   __device__ int64_t free_draw(uint32_t r, uint32_t cut) {
     if (L == 0u) return kFail;
     const uint32_t idx = (uint32_t)(((uint64_t)r * (uint64_t)L) >> 32);
-    const Ent e = live[idx];
+    // both entries are read before either is used
+    const Ent e = live_get(idx);
+    const Ent last = live_get(L - 1u);
     const uint32_t x = uniform(ent_a(e)), sz = uniform(ent_s(e));
     const uint32_t t = cut == 0u ? 0u : (uint32_t)(((uint64_t)cut * sz) >> 31);
-    const Ent last = live[L - 1u];
     mark(x + t, sz - t, true);
     if (t != 0u) {
-      live[idx] = mk_ent(x, t);
+      live_put(idx, mk_ent(x, t));
     } else {
-      live[idx] = mk_ent(uniform(ent_a(last)), uniform(ent_s(last)));
+      live_put(idx, mk_ent(uniform(ent_a(last)), uniform(ent_s(last))));
       --L;
     }
     return (int64_t)((uint64_t)(x + t) << shift);
@@ -355,7 +383,9 @@ struct BitHeap {
     if (lane == 0) lo[0] = L;
     for (uint32_t base = 0; base < L; base += 64u) {
       const uint32_t i = base + lane;
-      const Ent e = live[i < L ? i : 0u];
+      const uint32_t j = i < L ? i : 0u;
+      wave_sync();
+      const Ent e = j < kl ? llive[j] : live[j];
       if (i < L) {
         lo[1 + 2 * i] = (int64_t)((uint64_t)ent_a(e) << sh);
         lo[2 + 2 * i] = (int64_t)((uint64_t)ent_s(e) << sh);

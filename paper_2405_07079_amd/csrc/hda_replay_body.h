@@ -278,17 +278,20 @@ __device__ __forceinline__ void ord_any_heap(const ReplayParams& p, HDA_LDS uint
 }
 
 // Bitmask-allocator replay of one heap (hda_bitmap.h) in a workspace slot
-// of max_granules flags, their node summaries and p.cap_live live entries; a
+// of max_granules flags, their node summaries and p.cap_live live entries
+// (the first kn summaries and kl live entries in the wave's LDS instead); a
 // heap of another algorithm or a larger arena is rejected.
 __device__ __forceinline__ void bitmap_one_heap(const ReplayParams& p, uint64_t* bits,
                                                 uint64_t* nodes, Ent* live,
+                                                HDA_LDS uint64_t* lnodes, uint32_t kn,
+                                                HDA_LDS Ent* llive, uint32_t kl,
                                                 uint64_t max_granules, int64_t heap) {
   HeapRegs h;
   if (!heap_params(p, heap, h) || h.algo != kBitmap || (uint64_t)h.ag > max_granules) {
     reject_heap(p, heap);
     return;
   }
-  BitHeap w(bits, nodes, live, h, p.cap_live);
+  BitHeap w(bits, nodes, live, lnodes, kn, llive, kl, h, p.cap_live);
   w.init();
   int32_t st = 0;
   run_requests<kBitmap>(p, w, p.req_off[heap], p.req_off[heap + 1], h.shift, h.arena, st);

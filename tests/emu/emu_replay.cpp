@@ -32,6 +32,8 @@ struct LaneJob {
   Ent* live;
   uint64_t max_granules;
   uint8_t* ord_dev;      // ordered core: the wave's device slot
+  uint64_t* lnodes;      // bitmask allocator: the "LDS" summaries (3) and live entries (40)
+  Ent* llive;
 };
 LaneJob g_job;
 
@@ -55,7 +57,8 @@ void lane_main() {
     case 4: lean_any<4>(*g_job.p, *g_job.lds, *g_job.c, g_job.heap); break;
     case 6: ord_any_heap(*g_job.p, g_job.lds->base, g_job.ord_dev, g_job.heap); break;
     default:
-      bitmap_one_heap(*g_job.p, g_job.bits, g_job.nodes, g_job.live, g_job.max_granules,
+      bitmap_one_heap(*g_job.p, g_job.bits, g_job.nodes, g_job.live, g_job.lnodes, 3u,
+                      g_job.llive, 40u, g_job.max_granules,
                       g_job.heap);
       break;
   }
@@ -207,9 +210,16 @@ extern "C" int emu_replay(int64_t H, const int64_t* arena, const int64_t* align,
       std::vector<uint64_t> bits(nw + 1u, 0xA5A5A5A5A5A5A5A5ull);
       std::vector<uint64_t> nodes((nw + 63u) / 64u + 1u, 0xA5A5A5A5A5A5A5A5ull);
       std::vector<Ent> live(size_t(cap_live) + 1u, 0xA5A5A5A5A5A5A5A5ull);
+      // a few summaries and live entries in "LDS" (as the kernel keeps them),
+      // so that both places are exercised
+      std::vector<uint64_t> lnodes(3, 0xA5A5A5A5A5A5A5A5ull);
+      std::vector<Ent> llive(40, 0xA5A5A5A5A5A5A5A5ull);
       g_job = LaneJob{&p, &c, nullptr, h, shape, 0, bits.data(), nodes.data(), live.data(), ag};
+      g_job.lnodes = lnodes.data();
+      g_job.llive = llive.data();
       run_wave(w, stacks);
       n_sync = w.syncs;
+      for (uint64_t n = 0; n < 3 && n < nodes.size(); ++n) nodes[n] = lnodes[n];
       if (status[h] == 0 && !summaries_exact(bits.data(), nodes.data(), ag)) return 1;
     } else {
       g_job = LaneJob{&p, &c, nullptr, h, shape, 0};
