@@ -233,7 +233,14 @@ int hda_replay_per_heap(const hda_batch_desc *d, void *stream);
  * holds at once), each trace cut to its first 65,536 requests, at most 16 M
  * requests in all.  Candidates: 1, 2, 4, 8 or 16 heaps per workgroup x
  * (lds_free, lds_live) = (64, 512), (128, 1024), (256, 2048), (512, 4096),
- * those that fit the device's LDS.  The fastest is written to *out; put it
+ * those that fit the device's LDS; then, with the fastest of those, 0, 16,
+ * 64 or 128 heaps (the longest) on the ordered core (heavy_heaps, 64 KiB
+ * pools), timed on the 128 longest heaps with traces cut to 1 M requests
+ * (not tried when meta_free exceeds the 4,096 free blocks that core holds).
+ * A later call on a batch of the same shape on the same device (heap count,
+ * capacities, sample_heaps, reg_free, and every heap's trace length, arena,
+ * alignment and algorithm) returns the earlier choice without timing.  The
+ * fastest is written to *out; put it
  * into d->tuning (and size the workspace for it) before the replay.  The
  * caller's buffers are only read.  Temporary device memory is allocated and
  * freed here.  Synchronous.  HDA_E_INVAL for an invalid descriptor,

@@ -691,6 +691,32 @@ int time_candidates(const hda_batch_desc* d, const std::vector<int64_t>& off,
   return rc;
 }
 
+// Choices of earlier autotuner calls, keyed by the device and the batch's
+// shape (heap count, capacities, sample size, the caller's register tier,
+// and a hash of every heap's trace length, arena, alignment and algorithm):
+// a batch of the same shape on the same device reuses the choice without
+// timing again.  Any choice gives the same results.
+struct TuneKey {
+  int dev;
+  int64_t heaps, meta_free, meta_live;
+  int32_t sample, reg_free;
+  uint64_t shape;
+  bool operator==(const TuneKey& o) const {
+    return dev == o.dev && heaps == o.heaps && meta_free == o.meta_free &&
+           meta_live == o.meta_live && sample == o.sample && reg_free == o.reg_free &&
+           shape == o.shape;
+  }
+};
+constexpr size_t kTuneCacheMax = 64;  // shapes remembered; the oldest goes first
+std::mutex g_tune_mu;
+std::vector<std::pair<TuneKey, hda_tuning>> g_tune_cache;
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t n) {  // FNV-1a, 64 bits
+  const uint8_t* b = static_cast<const uint8_t*>(p);
+  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 0x100000001b3ull;
+  return h;
+}
+
 }  // namespace
 
 extern "C" {
@@ -716,6 +742,24 @@ int hda_replay_autotune(const hda_batch_desc* d, int32_t sample_heaps, void* str
       hipMemcpyAsync(algo.data(), d->algo, H * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return HDA_E_DEVICE;
+  TuneKey key{0, H, d->meta_free, d->meta_live, sample_heaps, d->tuning.reg_free, 0xcbf29ce484222325ull};
+  if (hipGetDevice(&key.dev) != hipSuccess) return HDA_E_DEVICE;
+  for (int64_t h = 0; h < H; ++h) {
+    const int64_t len = off[h + 1] - off[h];
+    key.shape = fnv1a(key.shape, &len, 8);
+    key.shape = fnv1a(key.shape, &arena[h], 8);
+    key.shape = fnv1a(key.shape, &align[h], 8);
+    key.shape = fnv1a(key.shape, &algo[h], 4);
+  }
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    for (const auto& e : g_tune_cache)
+      if (e.first == key) {
+        hda_batch_desc dp = *d;
+        dp.tuning = e.second;
+        return hda_replay_resolve(&dp, out);
+      }
+  }
   // 1. heaps per workgroup and the lean path's LDS residency, on the longest
   // heaps, as many as the device holds at once under the default tuning,
   // each trace cut to its first kCut requests
@@ -763,6 +807,11 @@ int hda_replay_autotune(const hda_batch_desc* d, int32_t sample_heaps, void* str
       if (rc != HDA_OK && rc != HDA_E_INVAL) return rc;
       if (rc == HDA_OK) pick = pick2;
     }
+  }
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    if (g_tune_cache.size() >= kTuneCacheMax) g_tune_cache.erase(g_tune_cache.begin());
+    g_tune_cache.push_back({key, pick});
   }
   hda_batch_desc dp = *d;
   dp.tuning = pick;

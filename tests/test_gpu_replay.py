@@ -300,3 +300,23 @@ def test_autotune_picks_a_valid_tuning():
     heaps = sorted(set(rng.choice(b.heaps, 60, replace=False).tolist())
                    | set(np.argsort(-lens)[:6].tolist()))
     check_against_oracle(b, res, hda.states_to_host(db), db.status.cpu().numpy(), heaps)
+
+
+def test_autotune_reuses_its_choice_for_the_same_shape():
+    """A second call on a batch of the same shape (here: the same batch,
+    and a copy with other requests but the same lengths and heaps) returns
+    the first call's choice from the cache, without timing again."""
+    import time
+    b = W.uneven_batch(heaps=384, len_scale=0.01, seed=13)
+    say(f"case: autotune cache, {b.heaps} heaps")
+    db = hda.upload(b)
+    t0 = time.perf_counter()
+    first = hda.hda_replay_autotune(db)
+    t1 = time.perf_counter()
+    again = hda.hda_replay_autotune(db)
+    t2 = time.perf_counter()
+    assert again == first
+    assert t2 - t1 < 0.5 * (t1 - t0)
+    other = W.Batch(b.name, b.arena, b.align, b.algo, b.req_off,
+                    np.where(b.req >= 0, b.req // 2 + 1, b.req), dict(b.meta))
+    assert hda.hda_replay_autotune(hda.upload(other)) == first
