@@ -1,8 +1,11 @@
-"""The 256 GiB segregated-fit heap (one wavefront, 50 M requests) on the GPU.
+"""The 256 GiB segregated-fit heap (one wavefront, 50 M requests) on the GPU,
+on the lean core and on the ordered core.
 
 Its tables peak at about 2,100 free and 13,300 live blocks, so the call asks
-for capacities of 4,096 / 16,384 and keeps both tables in one wave's LDS
-(1,920 free entries past the four register chunks, 16,384 live entries).
+for capacities of 4,096 / 16,384.  The lean core keeps both tables in one
+wave's LDS (1,920 free entries past the four register chunks, 16,384 live
+entries); the ordered core keeps its chunks, records and the first 10,624
+live entries in a 158 KiB pool and the rest in device memory.
 
 The prefix test compares every result and the final state with the oracle.
 The full-length test compares digests of all 50 M results and of the final
@@ -41,9 +44,14 @@ def prefix(b, n):
                    np.ascontiguousarray(b.req[:n]), dict(b.meta))
 
 
-def run(batch):
-    db = hda.upload(batch, tuning=TUNING, meta_free=META_FREE, meta_live=META_LIVE)
-    assert hda.hda_replay_resolve(db)["lds_live"] == 16384
+# the ordered core: one wave owning a workgroup's LDS (158 KiB)
+ORDERED = hda.tuning(heavy_heaps=1, heavy_kib=158)
+
+
+def run(batch, tuning=TUNING):
+    db = hda.upload(batch, tuning=tuning, meta_free=META_FREE, meta_live=META_LIVE)
+    r = hda.hda_replay_resolve(db)
+    assert r["lds_live"] == 16384 if tuning is TUNING else r["heavy_heaps"] == 1
     hda.hda_replay(db)
     torch.cuda.synchronize()
     return db.res.cpu().numpy(), hda.states_to_host(db)[0], int(db.status[0].item())
@@ -54,11 +62,12 @@ def large():
     return W.large_seg_fit()
 
 
-def test_large_seg_fit_prefix(large):
+@pytest.mark.parametrize("core", ("lean", "ordered"))
+def test_large_seg_fit_prefix(large, core):
     n = 2_000_000
     b = prefix(large, n)
-    say(f"case: 256 GiB segregated fit, first {n} requests")
-    res, st, status = run(b)
+    say(f"case: 256 GiB segregated fit, first {n} requests, {core} core")
+    res, st, status = run(b, TUNING if core == "lean" else ORDERED)
     ores, ost = oracle.replay_heap(W.SEG_FIT, int(b.arena[0]), int(b.align[0]), b.req)
     assert status == 0
     if not np.array_equal(res, ores):
@@ -67,12 +76,13 @@ def test_large_seg_fit_prefix(large):
     assert np.array_equal(st, ost)
 
 
-def test_large_seg_fit_full_length(large):
+@pytest.mark.parametrize("core", ("lean", "ordered"))
+def test_large_seg_fit_full_length(large, core):
     with open(os.path.join(HERE, "golden", "large_seg_fit_256GiB.json")) as f:
         g = json.load(f)
     assert digest(large.req) == g["trace_sha256"]
-    say("case: 256 GiB segregated fit, 50 M requests")
-    res, st, status = run(large)
+    say(f"case: 256 GiB segregated fit, 50 M requests, {core} core")
+    res, st, status = run(large, TUNING if core == "lean" else ORDERED)
     assert status == 0
     pos = np.array(g["sample_positions"])
     assert np.array_equal(res[pos], np.array(g["sample_results"]))
