@@ -360,7 +360,7 @@ struct LeanHeap {
   // Allocate sg granules; kreq is the request's byte class (segregated fit).
   // Returns the byte offset, -1, kENoMeta or kOverflow.
   __device__ __forceinline__ int64_t alloc(uint32_t sg, uint32_t kreq) {
-    uint32_t j, a, s;
+    uint32_t j = 0, a = 0, s = 0;
     if (!select(sg, kreq, j, a, s)) return kFail;
     if (L >= capL) return kENoMeta;
     if (L >= live_room) return kOverflow;
@@ -429,7 +429,7 @@ struct LeanHeap {
       const uint32_t lr = ctz64(MR), jr = 64u * (rdlane(cr, lr) - 1u) + lr;
       const uint32_t sl = size_at(jl), sr = size_at(jr), ms = sl + sz + sr;
       const uint32_t last = F - 1u;
-      uint32_t keep;  // slot that ends up holding the merged block
+      uint32_t keep = 0;  // slot that ends up holding the merged block
       if (jr == last) {
         keep = jl;
       } else if (jl == last) {

@@ -68,6 +68,12 @@ typedef uint32_t u32x4 __attribute__((vector_size(16)));
 // Wave-wide maximum of a u32 (every lane active).
 __device__ __forceinline__ uint32_t wave_max(uint32_t v) { return ~wave_min(~v); }
 
+// The lanes below n as a mask (n <= 64 or more): lane conditions of a ballot
+// are applied on the scalar side instead of being combined per lane.
+__device__ __forceinline__ uint64_t lanes_below(uint32_t n) {
+  return n >= 64u ? ~0ull : (1ull << n) - 1ull;
+}
+
 // Directory access: lane (i & 63) of register i >> 6.
 template <int D>
 __device__ __forceinline__ uint32_t dir_get(const uint32_t (&v)[D], uint32_t i) {
@@ -94,9 +100,8 @@ __device__ __forceinline__ void dir_insert(uint32_t (&v)[D], uint32_t i, uint32_
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     const uint32_t top = rdlane(v[k], 63);
-    const uint32_t up = shfl(v[k], lane == 0u ? 0u : lane - 1u);
+    const uint32_t moved = wave_shr1(carry, v[k]);  // lane 0 takes the carry
     const uint32_t g = 64u * (uint32_t)k + lane;
-    const uint32_t moved = lane == 0u ? carry : up;
     v[k] = g > i ? moved : (g == i ? x : v[k]);
     carry = top;
   }
@@ -109,9 +114,8 @@ __device__ __forceinline__ void dir_erase(uint32_t (&v)[D], uint32_t i, uint32_t
 #pragma unroll
   for (int k = 0; k < D; ++k) {
     const uint32_t next0 = k + 1 < D ? rdlane(v[k + 1 < D ? k + 1 : k], 0) : fill;
-    const uint32_t down = shfl(v[k], lane == 63u ? 63u : lane + 1u);
+    const uint32_t moved = wave_shl1(next0, v[k]);  // lane 63 takes the next register's lane 0
     const uint32_t g = 64u * (uint32_t)k + lane;
-    const uint32_t moved = lane == 63u ? next0 : down;
     v[k] = g >= i ? moved : v[k];
   }
 }
@@ -198,21 +202,23 @@ struct Hal {
   }
 
   // ---- keys ----
-  __device__ __forceinline__ static bool row_le(const Row& r, uint32_t k1, uint32_t k0) {
-    return KEY64 ? (r.s < k1 || (r.s == k1 && r.a <= k0)) : r.a <= k0;
-  }
-  __device__ __forceinline__ static bool row_lt(const Row& r, uint32_t k1, uint32_t k0) {
-    return KEY64 ? (r.s < k1 || (r.s == k1 && r.a < k0)) : r.a < k0;
+  // Lanes whose key (r1, r0) is <= (k1, k0) (strict: <); keyed by r0 alone
+  // unless KEY64.  Each comparison is one ballot; they are combined on the
+  // scalar side.
+  __device__ __forceinline__ static uint64_t key_ballot(uint32_t r1, uint32_t r0, uint32_t k1,
+                                                        uint32_t k0, bool strict) {
+    const uint64_t lo = strict ? ballot(r0 < k0) : ballot(r0 <= k0);
+    if constexpr (!KEY64) return lo;
+    return ballot(r1 < k1) | (ballot(r1 == k1) & lo);
   }
   // chunks whose first key is <= (k1, k0) (strict: <)
   __device__ __forceinline__ uint32_t count_first(uint32_t k1, uint32_t k0, bool strict) const {
     uint32_t n = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      const uint32_t g = 64u * (uint32_t)k + lane_id();
-      const bool le = KEY64 ? (dk1[k] < k1 || (dk1[k] == k1 && (strict ? dk0[k] < k0 : dk0[k] <= k0)))
-                            : (strict ? dk0[k] < k0 : dk0[k] <= k0);
-      n += (uint32_t)__builtin_popcountll(ballot(g < nc && le));
+      const uint32_t base = 64u * (uint32_t)k;
+      const uint64_t le = key_ballot(dk1[k], dk0[k], k1, k0, strict);
+      n += (uint32_t)__builtin_popcountll(le & lanes_below(nc > base ? nc - base : 0u));
     }
     return n;
   }
@@ -284,8 +290,9 @@ struct Hal {
   __device__ __forceinline__ void insert_at(uint32_t ci, uint32_t p, const Row& r, const Row& e) {
     const uint32_t lane = lane_id();
     const uint32_t n = count(ci), sl = slot(ci);
+    // the row moved up one lane (lane 0: the sentinel)
+    const Row up{wave_shr1(kNone, r.a), wave_shr1(kSentS, r.s)};
     if (n < 64u) {
-      const Row up = pull(r, lane - 1u, lane >= 1u);
       const Row o = pick(lane < p, r, pick(lane == p, e, up));
       store(sl, o);
       describe(ci, o, n + 1u);
@@ -294,8 +301,7 @@ struct Hal {
     // split: the 65 entries c[0..64] become 33 here and 32 in a new chunk
     // after it; c[i] = r[i] (i < p), e (i == p), r[i - 1] (i > p)
     const uint32_t ns = take_slot();
-    const Row lo_up = pull(r, lane - 1u, lane >= 1u);
-    Row left = pick(lane < p, r, pick(lane == p, e, lo_up));
+    Row left = pick(lane < p, r, pick(lane == p, e, up));
     left = pick(lane <= 32u, left, sentinel());
     const uint32_t i = lane + 33u;  // position in c of this lane's right entry
     const Row r_same = pull(r, i, i < 64u);
@@ -318,7 +324,8 @@ struct Hal {
   __device__ __forceinline__ void erase_at(uint32_t ci, uint32_t p, const Row& r) {
     const uint32_t lane = lane_id();
     const uint32_t n = count(ci) - 1u, sl = slot(ci);
-    const Row down = pull(r, lane + 1u, lane < 63u);
+    // the row moved down one lane (lane 63: the sentinel)
+    const Row down{wave_shl1(kNone, r.a), wave_shl1(kSentS, r.s)};
     const Row o = pick(lane >= p, down, r);
     if (n >= 32u || nc == 1u) {
       store(sl, o);
@@ -373,7 +380,7 @@ struct Hal {
     ci = c - 1u;
     r = load(slot(ci));
     const uint32_t n = count(ci);
-    p = (uint32_t)__builtin_popcountll(ballot(lane_id() < n && row_le(r, k1, k0))) - 1u;
+    p = (uint32_t)__builtin_popcountll(key_ballot(r.s, r.a, k1, k0, false) & lanes_below(n)) - 1u;
   }
   // Where a new key goes: chunk ci (the last one starting below it, else
   // the first), its row, and the position of the first entry above it.
@@ -383,7 +390,7 @@ struct Hal {
     ci = c == 0u ? 0u : c - 1u;
     r = load(slot(ci));
     const uint32_t n = count(ci);
-    p = (uint32_t)__builtin_popcountll(ballot(lane_id() < n && row_lt(r, k1, k0)));
+    p = (uint32_t)__builtin_popcountll(key_ballot(r.s, r.a, k1, k0, true) & lanes_below(n));
   }
   // (value, key) tables: insert and remove one key
   __device__ __forceinline__ void insert_key(uint32_t a, uint32_t s) {
@@ -404,8 +411,9 @@ struct Hal {
     uint32_t c = kNone;
 #pragma unroll
     for (int k = D - 1; k >= 0; --k) {
-      const uint32_t g = 64u * (uint32_t)k + lane_id();
-      const uint64_t m = ballot(g < nc && g >= from && dmx[k] >= sg);
+      const uint32_t base = 64u * (uint32_t)k;
+      const uint64_t m = ballot(dmx[k] >= sg) & lanes_below(nc > base ? nc - base : 0u) &
+                         ~lanes_below(from > base ? from - base : 0u);
       c = m != 0ull ? 64u * (uint32_t)k + ctz64(m) : c;
     }
     return c;
@@ -566,7 +574,7 @@ struct OrdHeap {
     else ((HDA_GLOBAL uint32_t*)(m.rec_g + i))[f & 3u] = x;
   }
   __device__ __forceinline__ uint32_t rec_take() {
-    const uint64_t m1 = ballot(frl != 0u || frh != 0u);
+    const uint64_t m1 = ballot((frl | frh) != 0u);
     const uint32_t l = m1 != 0ull ? ctz64(m1) : 63u;
     const uint32_t wl = rdlane(frl, l), wh = rdlane(frh, l);
     const uint32_t b = wl != 0u ? (uint32_t)__builtin_ctz(wl)
@@ -717,7 +725,6 @@ struct OrdHeap {
   }
 
   __device__ __forceinline__ int64_t alloc(uint32_t sg, uint32_t kreq) {
-    const uint32_t lane = lane_id();
     if (full_dir()) return kOverflow;
     if constexpr (ALGO == kFirstFit) {
       const uint32_t ci = ta.first_fit_chunk(sg, 0u);
@@ -738,7 +745,7 @@ struct OrdHeap {
       Row r;
       bool found = false;
       if (ci0 != kNone) {
-        const uint64_t fit = ballot(lane < ta.count(ci0) && lane > p0 && r0.s >= sg);
+        const uint64_t fit = ballot(r0.s >= sg) & lanes_below(ta.count(ci0)) & ~lanes_below(p0 + 1u);
         if (fit != 0ull) { ci = ci0; p = ctz64(fit); r = r0; found = true; }
       }
       if (!found) {
@@ -747,7 +754,7 @@ struct OrdHeap {
         if (c2 == kNone) return kFail;
         ci = c2;
         r = c2 == ci0 ? r0 : ta.load(ta.slot(c2));
-        p = ctz64(ballot(lane < ta.count(c2) && r.s >= sg));
+        p = ctz64(ballot(r.s >= sg) & lanes_below(ta.count(c2)));
       }
       const uint32_t e = rdlane(r.a, p), s = rdlane(r.s, p);
       if (L >= capL) return kENoMeta;

@@ -86,10 +86,14 @@ __device__ __forceinline__ uint32_t run_block(Core& w, uint32_t n, uint32_t w0, 
       r = w.alloc(v0, seg_like(ALGO) ? rdlane(w1, j) : 0u);
     }
     if (r == kOverflow) { done = j; break; }
-    if (r == kENoMeta && st == 0) st = (int32_t)kENoMeta;
     olo = put_lane(olo, j, (uint32_t)(uint64_t)r);
     ohi = put_lane(ohi, j, (uint32_t)((uint64_t)r >> 32));
   }
+  // the heap's status: its first capacity error, looked for once per block
+  // rather than once per request
+  const bool nometa = lane_id() < done && olo == (uint32_t)(uint64_t)kENoMeta &&
+                      ohi == (uint32_t)((uint64_t)kENoMeta >> 32);
+  if (st == 0 && ballot(nometa) != 0ull) st = (int32_t)kENoMeta;
   return done;
 }
 

@@ -1,5 +1,5 @@
 // Wavefront primitives for gfx950 (64 lanes): lane id, ballot, readlane,
-// readfirstlane, DPP row shift and ds_bpermute.  hda_core.h is written only
+// readfirstlane, DPP row and wave shifts and ds_bpermute.  hda_core.h is written only
 // against these names, so the same core can be compiled elsewhere with
 // another definition of them (the test-suite runs it on the CPU with a
 // lockstep emulation of a wave).
@@ -61,6 +61,16 @@ __device__ __forceinline__ uint32_t row_bcast15(uint32_t old, uint32_t src) {
 // under row mask 0b1100).
 __device__ __forceinline__ uint32_t row_bcast31(uint32_t old, uint32_t src) {
   return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x143, 0xc, 0xf, false);
+}
+
+// Whole-wave shifts by one lane (DPP wave_shr:1 / wave_shl:1): lane i
+// receives src from lane i - 1 (shr1) or i + 1 (shl1); the lane with no
+// source (0, resp. 63) receives `old`.
+__device__ __forceinline__ uint32_t wave_shr1(uint32_t old, uint32_t src) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ uint32_t wave_shl1(uint32_t old, uint32_t src) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)src, 0x130, 0xf, 0xf, false);
 }
 
 __device__ __forceinline__ uint32_t shfl(uint32_t v, uint32_t src_lane) {

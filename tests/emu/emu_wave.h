@@ -98,6 +98,16 @@ inline uint32_t row_bcast31(uint32_t old, uint32_t src) {
   });
 }
 
+// Whole-wave shifts by one lane; the lane with no source receives `old`.
+inline uint32_t wave_shr1(uint32_t old, uint32_t src) {
+  const uint32_t me = emu_lane;
+  return exchange(src, [me, old](const uint64_t* x) { return me >= 1u ? (uint32_t)x[me - 1u] : old; });
+}
+inline uint32_t wave_shl1(uint32_t old, uint32_t src) {
+  const uint32_t me = emu_lane;
+  return exchange(src, [me, old](const uint64_t* x) { return me <= 62u ? (uint32_t)x[me + 1u] : old; });
+}
+
 inline uint32_t shfl(uint32_t v, uint32_t src_lane) {
   return exchange(v, [src_lane](const uint64_t* x) { return (uint32_t)x[src_lane & 63u]; });
 }
