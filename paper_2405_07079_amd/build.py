@@ -14,6 +14,11 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
          # packed FP32 instructions stay off in every device compile
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # branches on wave-uniform values stay plain scalar branches: the
+         # cores branch only on uniform values, and structurizing those
+         # regions as if they could diverge made the request loops copy
+         # the heap's registers on every request
+         "-mllvm", "-structurizecfg-skip-uniform-regions=true",
          "-Wall", "-Wno-unused-function"]
 
 
