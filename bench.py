@@ -42,9 +42,11 @@ SALU_ISSUE_PEAK = 256 * 2.4e9
 
 
 def kernel_source_hash():
-    """sha256 over the kernel sources: counter figures recorded for other
-    sources no longer describe the kernel being timed."""
+    """sha256 over the kernel sources and the device compiler flags: counter
+    figures recorded for other sources or flags no longer describe the
+    kernel being timed."""
     import hashlib
+    from paper_2405_07079_amd import build as B
     d = os.path.join(ROOT, "paper_2405_07079_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(os.listdir(d)):
@@ -52,6 +54,7 @@ def kernel_source_hash():
             h.update(f.encode())
             with open(os.path.join(d, f), "rb") as fh:
                 h.update(fh.read())
+    h.update(" ".join(B.FLAGS).encode())
     return h.hexdigest()
 
 
