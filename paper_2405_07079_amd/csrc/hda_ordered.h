@@ -772,11 +772,13 @@ struct OrdHeap {
       }
       const uint32_t s = rdlane(r.s, p), e = rdlane(r.a, p);
       if (L >= capL) return kENoMeta;
-      tb.erase_at(ci, p, r);
-      if (s > sg) tb.insert_key(e, s - sg);
+      // the block's entry in the address table is looked up first: the key
+      // table's updates do not touch it, and its load then overlaps them
       uint32_t cj, q;
       Row ra;
       ta.locate(0u, e, cj, ra, q);
+      tb.erase_at(ci, p, r);
+      if (s > sg) tb.insert_key(e, s - sg);
       return commit_fit(cj, q, ra, e, s, sg);
     } else {
       // class of the first non-empty list at or above the request's
