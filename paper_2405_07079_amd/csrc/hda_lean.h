@@ -184,6 +184,20 @@ struct LeanHeap {
       k = kSeg ? uniform(ek) : 0u;
     }
   }
+  // The block (address, size) of free entry j.
+  __device__ __forceinline__ void read_block(uint32_t j, uint32_t& a, uint32_t& s) {
+    if (j < HF) {
+      const uint32_t r = j >> 6, l = j & 63u;
+      a = reg_lane(fa, r, l);
+      s = reg_lane(fs, r, l);
+    } else {
+      wave_sync();
+      uint32_t ea, es, ek;
+      cold_get(j - HF, ea, es, ek);
+      a = uniform(ea);
+      s = uniform(es);
+    }
+  }
   // The register chunks take a select each (none matches a cold index), so
   // the tables are never merged across a branch.  An LDS entry is stored by
   // every lane with the same value: a store guarded by a lane test would be
@@ -338,21 +352,23 @@ struct LeanHeap {
       // above the request's class
       if (kreq >= kClasses) return false;
       const uint32_t lo = kreq << kKeyShift;
-      uint32_t best = kNone, bc = 0, ba = 0, bsz = 0;  // the candidate's block
-      scan([&](uint32_t ch, uint32_t ea, uint32_t es, uint32_t ek) {
-        const uint32_t t = ek >= lo ? ek : kNone;
+      // Keys are compared as (key - lo) mod 2^32: keys below lo wrap past
+      // every key at or above it and past the empty slots' key ~0 (which
+      // maps to ~lo), so the smallest such value is the smallest key at or
+      // above lo whenever it is below ~lo.  Only the chunk is carried; the
+      // block is read from the chosen slot afterwards.
+      uint32_t best = kNone, bc = 0;
+      scan([&](uint32_t ch, uint32_t, uint32_t, uint32_t ek) {
+        const uint32_t t = ek - lo;
         const bool lt = t < best;
         best = lt ? t : best;
         bc = lt ? ch : bc;
-        ba = lt ? ea : ba;
-        bsz = lt ? es : bsz;
       });
       const uint32_t K = wave_min(best);
-      if (K == kNone) return false;
+      if (K >= ~lo) return false;
       const uint32_t l = ctz64(ballot(best == K));
       j = 64u * rdlane(bc, l) + l;
-      a = rdlane(ba, l);
-      s = rdlane(bsz, l);
+      read_block(j, a, s);
       return true;
     }
   }
