@@ -319,23 +319,22 @@ struct LeanHeap {
       a = ALGO == kFirstFit ? K : end - s;
       return true;
     } else if constexpr (ALGO == kBestFit) {
-      // smallest size, then lowest address; keyed by the leftover es - sg,
-      // which (sg >= 1) never equals kNone, as a whole-arena size of
-      // 2^32 - 1 granules would
-      // (leftover, address) compared as one 64-bit value: one vector compare
-      // per chunk, no mask logic on the scalar unit
+      // smallest size, then lowest address: (leftover, address) compared as
+      // one 64-bit value, one vector compare per chunk.  The leftover is
+      // es - sg mod 2^32: a block that fits leaves at most ~sg, one that
+      // does not (empty slots included, size 0) wraps to more, so no test
+      // of the size is needed per entry.
       uint64_t best = ~0ull;
       uint32_t bc = 0;
       scan([&](uint32_t c, uint32_t ea, uint32_t es, uint32_t) {
-        const uint32_t t = es >= sg ? es - sg : kNone;
-        const uint64_t key = ((uint64_t)t << 32) | ea;
+        const uint64_t key = ((uint64_t)(es - sg) << 32) | ea;
         const bool take = key < best;
         best = take ? key : best;
         bc = take ? c : bc;
       });
       const uint32_t bs = (uint32_t)(best >> 32), ba = (uint32_t)best;
       const uint32_t K = wave_min(bs);
-      if (K == kNone) return false;
+      if (K > ~sg) return false;
       uint64_t mk = ballot(bs == K);
       if (__builtin_popcountll(mk) > 1) {
         const uint32_t A2 = wave_min(bs == K ? ba : kNone);
