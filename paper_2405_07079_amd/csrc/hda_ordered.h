@@ -168,8 +168,13 @@ struct Hal {
     sl = sl < NC ? sl : NC - 1u;
     const uint32_t lane = lane_id();
     u32x2 v;
-    if (sl < nl) v = *(const HDA_LDS u32x2*)(lb + sl * CB + lane * 8u);
-    else v = *(const HDA_GLOBAL u32x2*)(gb + (uint64_t)sl * CB + lane * 8u);
+    if (sl < nl) {
+      v = *(const HDA_LDS u32x2*)(lb + sl * CB + lane * 8u);
+    } else {
+      v = *(const HDA_GLOBAL u32x2*)(gb + (uint64_t)sl * CB + lane * 8u);
+      settle(v[0]);
+      settle(v[1]);
+    }
     return Row{v[0], v[1]};
   }
   __device__ __forceinline__ void store(uint32_t sl, const Row& r) const {
@@ -530,7 +535,11 @@ struct OrdHeap {
   }
   __device__ __forceinline__ Ent lraw(uint32_t i) const {
     wave_sync();
-    return i < m.ll_n ? m.ll[i] : m.gl[i];
+    if (i < m.ll_n) return m.ll[i];
+    const Ent e = m.gl[i];
+    settle((uint32_t)e);
+    settle((uint32_t)(e >> 32));
+    return e;
   }
   __device__ __forceinline__ void lset(uint32_t i, Ent e) const {
     wave_sync();
@@ -551,7 +560,12 @@ struct OrdHeap {
     wave_sync();
     i = i < kOrdMaxFree ? i : kOrdMaxFree - 1u;
     u32x4 v;
-    if (i < m.rec_n) v = m.rec_l[i]; else v = m.rec_g[i];
+    if (i < m.rec_n) {
+      v = m.rec_l[i];
+    } else {
+      v = m.rec_g[i];
+      settle(v[0]); settle(v[1]); settle(v[2]); settle(v[3]);
+    }
     return v;
   }
   __device__ __forceinline__ static Rec rec_of(const u32x4& v) {

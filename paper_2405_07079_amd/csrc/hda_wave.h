@@ -77,6 +77,13 @@ __device__ __forceinline__ uint32_t shfl(uint32_t v, uint32_t src_lane) {
   return (uint32_t)__shfl((int)v, (int)src_lane);
 }
 
+// A value loaded from device memory is waited for here.  A table access
+// that goes to LDS or to device memory by a uniform branch waits inside its
+// device-memory branch, so that where the two paths join no device-memory
+// load is outstanding, and the LDS path waits only for LDS -- not for the
+// request prefetch or the result stores also counted by the same counter.
+__device__ __forceinline__ void settle(uint32_t v) { asm volatile("" ::"v"(v)); }
+
 // Ordering point between table accesses; lanes of a wave already execute in
 // lockstep on the hardware, so there is nothing to do here.
 __device__ __forceinline__ void wave_sync() {}

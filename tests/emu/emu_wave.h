@@ -69,6 +69,9 @@ inline uint32_t put_lane(uint32_t v, uint32_t l, uint32_t x) {
 // optimisation barrier on the GPU; nothing to do here
 inline uint32_t opaque(uint32_t v) { return v; }
 
+// a wait for a device-memory load on the GPU; nothing to do here
+inline void settle(uint32_t) {}
+
 // the first active lane; in the core this is only used with all lanes active
 inline uint32_t uniform(uint32_t v) { return rdlane(v, 0); }
 
