@@ -212,9 +212,10 @@ struct Hal {
   // scalar side.
   __device__ __forceinline__ static uint64_t key_ballot(uint32_t r1, uint32_t r0, uint32_t k1,
                                                         uint32_t k0, bool strict) {
-    const uint64_t lo = strict ? ballot(r0 < k0) : ballot(r0 <= k0);
-    if constexpr (!KEY64) return lo;
-    return ballot(r1 < k1) | (ballot(r1 == k1) & lo);
+    if constexpr (!KEY64) return strict ? ballot(r0 < k0) : ballot(r0 <= k0);
+    // (r1, r0) as one 64-bit value: one vector compare
+    const uint64_t r = ((uint64_t)r1 << 32) | r0, k = ((uint64_t)k1 << 32) | k0;
+    return strict ? ballot(r < k) : ballot(r <= k);
   }
   // chunks whose first key is <= (k1, k0) (strict: <)
   __device__ __forceinline__ uint32_t count_first(uint32_t k1, uint32_t k0, bool strict) const {
