@@ -121,8 +121,11 @@ struct LeanHeap {
   __device__ __forceinline__ void cold_get(uint32_t i, uint32_t& a, uint32_t& s,
                                            uint32_t& k) const {
     if constexpr (kSeg) {
-      const HDA_LDS SegRec* r = (HDA_LDS SegRec*)m.base + i;
-      a = r->a; s = r->s; k = r->k;
+      // the whole record in one 16-byte load (a 4-byte load of the key
+      // alone, 16 bytes apart per lane, meets bank conflicts)
+      typedef uint32_t rec4 __attribute__((vector_size(16)));
+      const rec4 v = *((const HDA_LDS rec4*)m.base + i);
+      a = v[0]; s = v[1]; k = v[2];
     } else {
       const Ent e = ((HDA_LDS Ent*)m.base)[i];
       a = ent_a(e); s = ent_s(e); k = 0u;
