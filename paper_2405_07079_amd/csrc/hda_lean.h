@@ -266,6 +266,7 @@ struct LeanHeap {
 
   // Remove free entry j: the last entry moves into its place and the last
   // slot is cleared.
+  template <bool CHK = true>
   __device__ __forceinline__ void remove(uint32_t j) {
     // no branch on j == last: moving the last entry onto itself is harmless,
     // and a branch here made the compiler copy the register chunks
@@ -275,7 +276,7 @@ struct LeanHeap {
     write(j, a, s, k);
     clear(last);
     F = last;
-    set_room();
+    if (CHK) set_room();
   }
 
   // Selection.  On success j is the chosen entry and (a, s) its block.
@@ -377,16 +378,20 @@ struct LeanHeap {
 
   // Allocate sg granules; kreq is the request's byte class (segregated fit).
   // Returns the byte offset, -1, kENoMeta or kOverflow.
+  // CHK = false: the caller has established that no request of the current
+  // block can outgrow the tiers (block_safe), so the overflow checks and the
+  // upkeep of live_room are left out; live_room is refreshed after the block.
+  template <bool CHK = true>
   __device__ __forceinline__ int64_t alloc(uint32_t sg, uint32_t kreq) {
     uint32_t j = 0, a = 0, s = 0;
     if (!select(sg, kreq, j, a, s)) return kFail;
     if (L >= capL) return kENoMeta;
-    if (L >= live_room) return kOverflow;
+    if (CHK && L >= live_room) return kOverflow;
     if (s > sg) {  // Alg. 1 / Alg. 4: the block is cut from the low end
-      if (kSeg && clock >= kStampLimit) return kOverflow;
+      if (CHK && kSeg && clock >= kStampLimit) return kOverflow;
       write(j, a + sg, s - sg, kSeg ? seg_key(s - sg) : 0u);
     } else {
-      remove(j);
+      remove<CHK>(j);
     }
     live_write(L, a, sg);
     ++L;
@@ -400,8 +405,9 @@ struct LeanHeap {
   // entry or, for a whole free, drop it from the live table (the last one
   // moves into its place).  Returns the byte offset of the released part,
   // kENoMeta or kOverflow.
+  template <bool CHK = true>
   __device__ __forceinline__ int64_t free_index(uint32_t idx, uint32_t cut) {
-    if (kSeg && clock >= kStampLimit) return kOverflow;
+    if (CHK && kSeg && clock >= kStampLimit) return kOverflow;
     // The victim and the last live entry (which takes the victim's slot at
     // the end) are read together, so the second load's latency hides behind
     // the first; nothing below writes the live table before that move.
@@ -426,14 +432,14 @@ struct LeanHeap {
     if ((ML | MR) == 0ull) {
       if (F >= capF) return kENoMeta;
       // (the freed block still counts as live here: the check is on the safe side)
-      if (need_bytes(F + 1u, L) > m.bytes) return kOverflow;
+      if (CHK && need_bytes(F + 1u, L) > m.bytes) return kOverflow;
       if (F >= HF && ((F - HF) & 63u) == 0u) {  // a new LDS chunk: its slots start empty
         wave_sync();
         cold_put(F - HF + lane_id(), kNone, 0u, kNone);
       }
       write(F, x, sz, kSeg ? seg_key(sz) : 0u);
       ++F;
-      set_room();
+      if (CHK) set_room();
     } else if (MR == 0ull) {
       const uint32_t l = ctz64(ML), jl = 64u * (rdlane(cl, l) - 1u) + l;
       const uint32_t sl = size_at(jl);
@@ -461,7 +467,7 @@ struct LeanHeap {
       write(keep, x - sl, ms, kSeg ? seg_key(ms) : 0u);
       clear(last);
       F = last;
-      set_room();
+      if (CHK) set_room();
     }
     if (t != 0u) {
       live_write(idx, bx, t);
@@ -474,9 +480,18 @@ struct LeanHeap {
 
   // Replay free: r is the 32-bit draw, the victim is live[(r * L) >> 32];
   // cut as in free_index; nothing live -> -1.
+  template <bool CHK = true>
   __device__ __forceinline__ int64_t free_draw(uint32_t r, uint32_t cut) {
     if (L == 0u) return kFail;
-    return free_index((uint32_t)(((uint64_t)r * (uint64_t)L) >> 32), cut);
+    return free_index<CHK>((uint32_t)(((uint64_t)r * (uint64_t)L) >> 32), cut);
+  }
+
+  // Whether the next n (<= 64) requests can skip the overflow checks: each
+  // adds at most one live entry and one free entry, n free entries open at
+  // most one new LDS chunk (64 entries of kRec bytes, the room of 8 kRec
+  // live entries), and each takes at most one push stamp.
+  __device__ __forceinline__ bool block_safe(uint32_t n) const {
+    return L + n + 8u * kRec <= live_room && (!kSeg || clock + n < kStampLimit);
   }
 
   // Hand this heap over to the general core (hda_core.h) on tiers `c` with

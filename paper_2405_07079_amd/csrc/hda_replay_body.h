@@ -64,13 +64,25 @@ __device__ __forceinline__ bool heap_params(const ReplayParams& p, int64_t heap,
   return true;
 }
 
+// Whether Core is the lean core, whose blocks may run without overflow checks.
+template <typename Core>
+struct IsLean {
+  static constexpr bool value = false;
+};
+template <int A, int R>
+struct IsLean<LeanHeap<A, R>> {
+  static constexpr bool value = true;
+};
+
 // Requests j < n of one block of 64 on core w: lane j of w0 holds request
 // j's draw (free) or size in granules (allocation, 0 = larger than the
 // arena), lane j of w1 its byte class (segregated fit) or its cut (free,
 // other fits; read only when CUT), bit j of mfree marks the frees.  Results
 // go to lane j of olo / ohi.  Returns the number of requests run: n, or the
-// index of the request that found the lean core's tiers too small.
-template <int ALGO, bool CUT, typename Core>
+// index of the request that found the lean core's tiers too small.  UNCHK:
+// the lean core's block_safe holds for the block, so no request can find the
+// tiers too small and the checks are compiled out.
+template <int ALGO, bool CUT, bool UNCHK, typename Core>
 __device__ __forceinline__ uint32_t run_block(Core& w, uint32_t n, uint32_t w0, uint32_t w1,
                                               uint64_t mfree, uint32_t& olo, uint32_t& ohi,
                                               int32_t& st) {
@@ -79,13 +91,15 @@ __device__ __forceinline__ uint32_t run_block(Core& w, uint32_t n, uint32_t w0, 
     const uint32_t v0 = rdlane(w0, j);
     int64_t r;
     if ((mfree >> j) & 1ull) {
-      r = w.free_draw(v0, CUT ? rdlane(w1, j) : 0u);
+      if constexpr (UNCHK) r = w.template free_draw<false>(v0, CUT ? rdlane(w1, j) : 0u);
+      else r = w.free_draw(v0, CUT ? rdlane(w1, j) : 0u);
     } else if (v0 == 0u) {
       r = kFail;
     } else {
-      r = w.alloc(v0, seg_like(ALGO) ? rdlane(w1, j) : 0u);
+      if constexpr (UNCHK) r = w.template alloc<false>(v0, seg_like(ALGO) ? rdlane(w1, j) : 0u);
+      else r = w.alloc(v0, seg_like(ALGO) ? rdlane(w1, j) : 0u);
     }
-    if (r == kOverflow) { done = j; break; }
+    if (!UNCHK && r == kOverflow) { done = j; break; }
     olo = put_lane(olo, j, (uint32_t)(uint64_t)r);
     ohi = put_lane(ohi, j, (uint32_t)((uint64_t)r >> 32));
   }
@@ -131,11 +145,22 @@ __device__ __forceinline__ int64_t run_requests(const ReplayParams& p, Core& w, 
     const uint32_t n = (uint32_t)min<int64_t>(64, to - base);
     uint32_t olo = 0, ohi = 0;
     // a block whose frees carry no cut runs a copy with the partial-free
-    // logic folded away
-    const uint32_t done =
-        (!seg_like(ALGO) && ballot(is_free && w1 != 0u) != 0ull)
-            ? run_block<ALGO, !seg_like(ALGO)>(w, n, w0, w1, mfree, olo, ohi, st)
-            : run_block<ALGO, false>(w, n, w0, w1, mfree, olo, ohi, st);
+    // logic folded away; on the lean core, such a block that cannot outgrow
+    // the tiers also runs without the overflow checks
+    const bool cut = !seg_like(ALGO) && ballot(is_free && w1 != 0u) != 0ull;
+    uint32_t done;
+    if (cut) {
+      done = run_block<ALGO, !seg_like(ALGO), false>(w, n, w0, w1, mfree, olo, ohi, st);
+    } else if constexpr (IsLean<Core>::value) {
+      if (w.block_safe(n)) {
+        done = run_block<ALGO, false, true>(w, n, w0, w1, mfree, olo, ohi, st);
+        w.set_room();
+      } else {
+        done = run_block<ALGO, false, false>(w, n, w0, w1, mfree, olo, ohi, st);
+      }
+    } else {
+      done = run_block<ALGO, false, false>(w, n, w0, w1, mfree, olo, ohi, st);
+    }
     if (lane < done) p.res[base + lane] = (int64_t)(((uint64_t)ohi << 32) | olo);
     if (done < n) return base + done;
   }
