@@ -739,8 +739,11 @@ struct OrdHeap {
     t.nc = o.nc;
   }
 
+  // CHK = false: block_safe holds for the current block, so no request of
+  // it finds a table at the directory's limit.
+  template <bool CHK = true>
   __device__ __forceinline__ int64_t alloc(uint32_t sg, uint32_t kreq) {
-    if (full_dir()) return kOverflow;
+    if (CHK && full_dir()) return kOverflow;
     if constexpr (ALGO == kFirstFit) {
       const uint32_t ci = ta.first_fit_chunk(sg, 0u);
       if (ci == kNone) return kFail;
@@ -950,8 +953,9 @@ struct OrdHeap {
   // Free live entry idx except its first floor(cut * size / 2^31) granules
   // (partial deallocation, sequential fits; cut < 2^31).  Returns the byte
   // offset of the released part or kENoMeta.
+  template <bool CHK = true>
   __device__ __forceinline__ int64_t free_index(uint32_t idx, uint32_t cut) {
-    if (full_dir()) return kOverflow;
+    if (CHK && full_dir()) return kOverflow;
     const uint32_t last = L - 1u;
     // both entries are loaded before either is used, so their latencies
     // overlap
@@ -971,10 +975,19 @@ struct OrdHeap {
     return (int64_t)((uint64_t)x << shift);
   }
 
+  template <bool CHK = true>
   __device__ __forceinline__ int64_t free_draw(uint32_t r, uint32_t cut) {
     if (L == 0u) return kFail;
-    return free_index((uint32_t)(((uint64_t)r * (uint64_t)L) >> 32), cut);
+    return free_index<CHK>((uint32_t)(((uint64_t)r * (uint64_t)L) >> 32), cut);
   }
+
+  // Whether the next n requests can skip the directory check: each adds at
+  // most one chunk to each table (one split), so none of them starts with a
+  // table at 64 D chunks.  (With the widest directory there is no check.)
+  __device__ __forceinline__ bool block_safe(uint32_t n) const {
+    return D >= kOrdDir || (ta.nc + n <= 64u * D && (!kKeys || tb.nc + n <= 64u * D));
+  }
+  __device__ __forceinline__ void set_room() {}  // nothing to refresh after a block
 
   // Canonical state (format in hda.h).
   __device__ __forceinline__ int64_t dump(int64_t* out, int64_t cap) {

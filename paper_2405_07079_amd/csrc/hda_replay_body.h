@@ -64,13 +64,18 @@ __device__ __forceinline__ bool heap_params(const ReplayParams& p, int64_t heap,
   return true;
 }
 
-// Whether Core is the lean core, whose blocks may run without overflow checks.
+// Whether Core's blocks may run without the checks that end a core's run
+// (the lean core's tiers, the ordered core's directory).
 template <typename Core>
-struct IsLean {
+struct UncheckedBlocks {
   static constexpr bool value = false;
 };
 template <int A, int R>
-struct IsLean<LeanHeap<A, R>> {
+struct UncheckedBlocks<LeanHeap<A, R>> {
+  static constexpr bool value = true;
+};
+template <int A, int D>
+struct UncheckedBlocks<OrdHeap<A, D>> {
   static constexpr bool value = true;
 };
 
@@ -80,8 +85,9 @@ struct IsLean<LeanHeap<A, R>> {
 // other fits; read only when CUT), bit j of mfree marks the frees.  Results
 // go to lane j of olo / ohi.  Returns the number of requests run: n, or the
 // index of the request that found the lean core's tiers too small.  UNCHK:
-// the lean core's block_safe holds for the block, so no request can find the
-// tiers too small and the checks are compiled out.
+// the core's block_safe holds for the block, so no request can find the
+// tiers (or the ordered core's directory) too small and the checks are
+// compiled out.
 template <int ALGO, bool CUT, bool UNCHK, typename Core>
 __device__ __forceinline__ uint32_t run_block(Core& w, uint32_t n, uint32_t w0, uint32_t w1,
                                               uint64_t mfree, uint32_t& olo, uint32_t& ohi,
@@ -145,13 +151,13 @@ __device__ __forceinline__ int64_t run_requests(const ReplayParams& p, Core& w, 
     const uint32_t n = (uint32_t)min<int64_t>(64, to - base);
     uint32_t olo = 0, ohi = 0;
     // a block whose frees carry no cut runs a copy with the partial-free
-    // logic folded away; on the lean core, such a block that cannot outgrow
-    // the tiers also runs without the overflow checks
+    // logic folded away; on the lean and ordered cores, such a block that
+    // cannot outgrow the tiers (the directory) also runs without the checks
     const bool cut = !seg_like(ALGO) && ballot(is_free && w1 != 0u) != 0ull;
     uint32_t done;
     if (cut) {
       done = run_block<ALGO, !seg_like(ALGO), false>(w, n, w0, w1, mfree, olo, ohi, st);
-    } else if constexpr (IsLean<Core>::value) {
+    } else if constexpr (UncheckedBlocks<Core>::value) {
       if (w.block_safe(n)) {
         done = run_block<ALGO, false, true>(w, n, w0, w1, mfree, olo, ohi, st);
         w.set_room();
