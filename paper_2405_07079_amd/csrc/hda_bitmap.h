@@ -297,6 +297,8 @@ struct BitHeap {
   }
 
   // Allocate sg granules (sg >= 1).  Returns the byte offset, -1 or kENoMeta.
+  // (CHK: no request of this core ends its run, so there is nothing to check)
+  template <bool CHK = true>
   __device__ int64_t alloc(uint32_t sg, uint32_t) {
     if (sg > ag) return kFail;
     uint32_t p = find(rover, sg);
@@ -314,6 +316,7 @@ struct BitHeap {
   // Replay free: the victim is live[(r * L) >> 32]; it keeps its first
   // floor(cut * size / 2^31) granules (partial deallocation); nothing live
   // -> -1.  Returns the byte offset of the freed part.
+  template <bool CHK = true>
   __device__ int64_t free_draw(uint32_t r, uint32_t cut) {
     if (L == 0u) return kFail;
     const uint32_t idx = (uint32_t)(((uint64_t)r * (uint64_t)L) >> 32);
@@ -331,6 +334,10 @@ struct BitHeap {
     }
     return (int64_t)((uint64_t)(x + t) << shift);
   }
+
+  // Every block may run without the run-ending checks of the other cores.
+  __device__ __forceinline__ bool block_safe(uint32_t) const { return true; }
+  __device__ __forceinline__ void set_room() {}
 
   // Canonical state (format in hda.h): the free runs in address order, the
   // live table, the rover.

@@ -78,6 +78,10 @@ template <int A, int D>
 struct UncheckedBlocks<OrdHeap<A, D>> {
   static constexpr bool value = true;
 };
+template <>
+struct UncheckedBlocks<BitHeap> {
+  static constexpr bool value = true;
+};
 
 // Requests j < n of one block of 64 on core w: lane j of w0 holds request
 // j's draw (free) or size in granules (allocation, 0 = larger than the
