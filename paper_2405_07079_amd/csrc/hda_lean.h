@@ -379,13 +379,14 @@ struct LeanHeap {
   // Allocate sg granules; kreq is the request's byte class (segregated fit).
   // Returns the byte offset, -1, kENoMeta or kOverflow.
   // CHK = false: the caller has established that no request of the current
-  // block can outgrow the tiers (block_safe), so the overflow checks and the
-  // upkeep of live_room are left out; live_room is refreshed after the block.
+  // block can outgrow the tiers or reach the capacities (block_safe), so
+  // those checks and the upkeep of live_room are left out; live_room is
+  // refreshed after the block.
   template <bool CHK = true>
   __device__ __forceinline__ int64_t alloc(uint32_t sg, uint32_t kreq) {
     uint32_t j = 0, a = 0, s = 0;
     if (!select(sg, kreq, j, a, s)) return kFail;
-    if (L >= capL) return kENoMeta;
+    if (CHK && L >= capL) return kENoMeta;
     if (CHK && L >= live_room) return kOverflow;
     if (s > sg) {  // Alg. 1 / Alg. 4: the block is cut from the low end
       if (CHK && kSeg && clock >= kStampLimit) return kOverflow;
@@ -430,7 +431,7 @@ struct LeanHeap {
     });
     const uint64_t ML = ballot(cl != 0u), MR = ballot(cr != 0u);
     if ((ML | MR) == 0ull) {
-      if (F >= capF) return kENoMeta;
+      if (CHK && F >= capF) return kENoMeta;
       // (the freed block still counts as live here: the check is on the safe side)
       if (CHK && need_bytes(F + 1u, L) > m.bytes) return kOverflow;
       if (F >= HF && ((F - HF) & 63u) == 0u) {  // a new LDS chunk: its slots start empty
@@ -486,12 +487,13 @@ struct LeanHeap {
     return free_index<CHK>((uint32_t)(((uint64_t)r * (uint64_t)L) >> 32), cut);
   }
 
-  // Whether the next n (<= 64) requests can skip the overflow checks: each
-  // adds at most one live entry and one free entry, n free entries open at
-  // most one new LDS chunk (64 entries of kRec bytes, the room of 8 kRec
-  // live entries), and each takes at most one push stamp.
+  // Whether the next n (<= 64) requests can skip the overflow and capacity
+  // checks: each adds at most one live entry and one free entry, n free
+  // entries open at most one new LDS chunk (64 entries of kRec bytes, the
+  // room of 8 kRec live entries), and each takes at most one push stamp.
   __device__ __forceinline__ bool block_safe(uint32_t n) const {
-    return L + n + 8u * kRec <= live_room && (!kSeg || clock + n < kStampLimit);
+    return L + n + 8u * kRec <= live_room && L + n <= capL && F + n <= capF &&
+           (!kSeg || clock + n < kStampLimit);
   }
 
   // Hand this heap over to the general core (hda_core.h) on tiers `c` with

@@ -740,7 +740,7 @@ struct OrdHeap {
   }
 
   // CHK = false: block_safe holds for the current block, so no request of
-  // it finds a table at the directory's limit.
+  // it finds a table at the directory's limit or reaches a capacity.
   template <bool CHK = true>
   __device__ __forceinline__ int64_t alloc(uint32_t sg, uint32_t kreq) {
     if (CHK && full_dir()) return kOverflow;
@@ -750,7 +750,7 @@ struct OrdHeap {
       const Row r = ta.load(ta.slot(ci));
       const uint32_t p = ctz64(ballot(r.s >= sg));
       const uint32_t e = rdlane(r.a, p), s = rdlane(r.s, p);
-      if (L >= capL) return kENoMeta;
+      if (CHK && L >= capL) return kENoMeta;
       return commit_fit(ci, p, r, e, s, sg);
     } else if constexpr (ALGO == kNextFit) {
       // the search starts at the first block ending past the rover (R9-R11)
@@ -775,7 +775,7 @@ struct OrdHeap {
         p = ctz64(ballot(r.s >= sg) & lanes_below(ta.count(c2)));
       }
       const uint32_t e = rdlane(r.a, p), s = rdlane(r.s, p);
-      if (L >= capL) return kENoMeta;
+      if (CHK && L >= capL) return kENoMeta;
       return commit_fit(ci, p, r, e, s, sg);
     } else if constexpr (ALGO == kBestFit) {
       // smallest key (size, end) at or above (sg, 0)
@@ -789,7 +789,7 @@ struct OrdHeap {
         p = 0u;
       }
       const uint32_t s = rdlane(r.s, p), e = rdlane(r.a, p);
-      if (L >= capL) return kENoMeta;
+      if (CHK && L >= capL) return kENoMeta;
       // the block's entry in the address table is looked up first: the key
       // table's updates do not touch it, and its load then overlaps them
       uint32_t cj, q;
@@ -821,7 +821,7 @@ struct OrdHeap {
       }
       const uint32_t i = head(c);
       const Rec b = rec(i);
-      if (L >= capL) return kENoMeta;
+      if (CHK && L >= capL) return kENoMeta;
       // pop the head (Alg. 4), keeping the lists' invariants (R20)
       set_head(c, b.nx);
       if (b.nx == kNone) bit_clear(c); else rec_link(b.nx, 3u, kNone);
@@ -846,6 +846,7 @@ struct OrdHeap {
   // Release [x, x + sz) into the free blocks, merging with free neighbours
   // (Alg. 2 / Alg. 5).  Returns false, changing nothing, when a new free
   // entry would exceed the capacity.
+  template <bool CHK = true>
   __device__ __forceinline__ bool release(uint32_t x, uint32_t sz) {
     const uint32_t lane = lane_id();
     const uint32_t xe = x + sz;
@@ -886,7 +887,7 @@ struct OrdHeap {
       sr = vr;
       hasR = rci != kNone && er - vr == xe;
     }
-    if (!hasL && !hasR && F >= capF) return false;
+    if (CHK && !hasL && !hasR && F >= capF) return false;
     const uint32_t ma = hasL ? x - sl : x;
     const uint32_t ms = (hasL ? sl : 0u) + sz + (hasR ? sr : 0u);
     const uint32_t me = hasR ? er : xe;  // end of the merged block
@@ -965,7 +966,7 @@ struct OrdHeap {
     const uint32_t bx = ent_a(v), bsz = ent_s(v);
     const uint32_t t = (kSeg || cut == 0u) ? 0u : (uint32_t)(((uint64_t)cut * bsz) >> 31);
     const uint32_t x = bx + t, sz = bsz - t;
-    if (!release(x, sz)) return kENoMeta;
+    if (!release<CHK>(x, sz)) return kENoMeta;
     if (t != 0u) {
       lset(idx, mk_ent(bx, t));
     } else {
@@ -981,11 +982,14 @@ struct OrdHeap {
     return free_index<CHK>((uint32_t)(((uint64_t)r * (uint64_t)L) >> 32), cut);
   }
 
-  // Whether the next n requests can skip the directory check: each adds at
-  // most one chunk to each table (one split), so none of them starts with a
-  // table at 64 D chunks.  (With the widest directory there is no check.)
+  // Whether the next n requests can skip the directory and capacity checks:
+  // each adds at most one chunk to each table (one split), one live entry
+  // and one free block, so none of them starts with a table at 64 D chunks
+  // or reaches a capacity.  (With the widest directory there is no
+  // directory check.)
   __device__ __forceinline__ bool block_safe(uint32_t n) const {
-    return D >= kOrdDir || (ta.nc + n <= 64u * D && (!kKeys || tb.nc + n <= 64u * D));
+    return L + n <= capL && F + n <= capF &&
+           (D >= kOrdDir || (ta.nc + n <= 64u * D && (!kKeys || tb.nc + n <= 64u * D)));
   }
   __device__ __forceinline__ void set_room() {}  // nothing to refresh after a block
 
