@@ -483,16 +483,17 @@ struct LeanHeap {
   // cut as in free_index; nothing live -> -1.
   template <bool CHK = true>
   __device__ __forceinline__ int64_t free_draw(uint32_t r, uint32_t cut) {
-    if (L == 0u) return kFail;
+    if (CHK && L == 0u) return kFail;
     return free_index<CHK>((uint32_t)(((uint64_t)r * (uint64_t)L) >> 32), cut);
   }
 
   // Whether the next n (<= 64) requests can skip the overflow and capacity
   // checks: each adds at most one live entry and one free entry, n free
   // entries open at most one new LDS chunk (64 entries of kRec bytes, the
-  // room of 8 kRec live entries), and each takes at most one push stamp.
+  // room of 8 kRec live entries), and each takes at most one push stamp;
+  // with n live blocks to start from, no free finds the live table empty.
   __device__ __forceinline__ bool block_safe(uint32_t n) const {
-    return L + n + 8u * kRec <= live_room && L + n <= capL && F + n <= capF &&
+    return L + n + 8u * kRec <= live_room && L + n <= capL && F + n <= capF && L >= n &&
            (!kSeg || clock + n < kStampLimit);
   }
 

@@ -978,18 +978,21 @@ struct OrdHeap {
 
   template <bool CHK = true>
   __device__ __forceinline__ int64_t free_draw(uint32_t r, uint32_t cut) {
-    if (L == 0u) return kFail;
+    if (CHK && L == 0u) return kFail;
     return free_index<CHK>((uint32_t)(((uint64_t)r * (uint64_t)L) >> 32), cut);
   }
 
   // Whether the next n requests can skip the directory and capacity checks:
-  // each adds at most one chunk to each table (one split), one live entry
-  // and one free block, so none of them starts with a table at 64 D chunks
-  // or reaches a capacity.  (With the widest directory there is no
+  // each adds at most one live entry and one free block, so none of them
+  // reaches a capacity, and with n live blocks to start from no free finds
+  // the live table empty.  Every chunk of a table holds at least 32 entries
+  // once there are two, so a table with fewer than 32 x 64 D free blocks has
+  // fewer than 64 D chunks: with F + n below that, no request starts with a
+  // table at the directory's limit.  (With the widest directory there is no
   // directory check.)
   __device__ __forceinline__ bool block_safe(uint32_t n) const {
-    return L + n <= capL && F + n <= capF &&
-           (D >= kOrdDir || (ta.nc + n <= 64u * D && (!kKeys || tb.nc + n <= 64u * D)));
+    return L + n <= capL && F + n <= capF && L >= n &&
+           (D >= kOrdDir || F + n < 32u * 64u * D);
   }
   __device__ __forceinline__ void set_room() {}  // nothing to refresh after a block
 
