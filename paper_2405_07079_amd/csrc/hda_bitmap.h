@@ -276,10 +276,12 @@ struct BitHeap {
     for (uint32_t n = p >> 12; n <= (last >> 6); ++n) {
       const uint32_t wi = 64u * n + lane_id();
       const bool in = wi >= first && wi <= last;
-      const uint64_t b0 = 64ull * wi;
-      const uint32_t lo = (uint32_t)((uint64_t)p > b0 ? (uint64_t)p - b0 : 0ull);
-      const uint64_t e = (uint64_t)p + s - b0;
-      const uint32_t hi = (uint32_t)(e < 64ull ? e : 64ull);
+      // 32-bit: 64 wi and p + s stay below 2^32; for a word in the range
+      // lo is 0..63 and e at least 1, and other words are masked off below
+      const uint32_t b0 = 64u * wi;
+      const uint32_t lo = p > b0 ? p - b0 : 0u;
+      const uint32_t e = p + s - b0;
+      const uint32_t hi = e < 64u ? e : 64u;
       const uint64_t m = in ? (hi == 64u ? ~0ull : (1ull << hi) - 1ull) & ~((1ull << (lo & 63u)) - 1ull)
                             : 0ull;
       uint64_t v;
