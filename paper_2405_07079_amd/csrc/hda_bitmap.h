@@ -193,8 +193,10 @@ struct BitHeap {
   // p + s - 1 lies in the node, with `carry` free granules in a row ending
   // just below the node (granules below lo count as used), or kNone; carry
   // becomes the free run ending at the node's top.
+  // Run lengths and granule indexes are 32-bit: a run of free granules is
+  // at most the arena's ag < 2^32 granules, and 64 wi < 2^32.
   __device__ __forceinline__ uint32_t word_step(uint32_t n, uint32_t lo, uint32_t s,
-                                                uint64_t& carry) {
+                                                uint32_t& carry) {
     const uint32_t lane = lane_id();
     const uint32_t wi = 64u * n + lane;
     const uint32_t lw = lo >> 6;
@@ -208,10 +210,10 @@ struct BitHeap {
     const uint64_t lt = ballot(!full) & ((1ull << lane) - 1ull);
     const uint32_t ps = lt ? 63u - clz64u(lt) : 0u;
     const uint32_t tp = shfl(top1, ps);
-    const uint64_t pre = lt ? (uint64_t)tp + 64ull * (lane - 1u - ps) : carry + 64ull * lane;
-    const uint64_t base = 64ull * wi;
+    const uint32_t pre = lt ? tp + 64u * (lane - 1u - ps) : carry + 64u * lane;
+    const uint32_t base = 64u * wi;
     // a run that reaches s in this word, having started below it
-    uint32_t cand = (pre < s && pre + low1 >= s) ? (uint32_t)(base - pre) : kNone;
+    uint32_t cand = (pre < s && pre + low1 >= s) ? base - pre : kNone;
     // a run of s inside this word
     if (s <= 64u) {
       uint64_t y = w;
@@ -220,11 +222,11 @@ struct BitHeap {
         y &= y >> d;
         k += d;
       }
-      const uint32_t in = y ? (uint32_t)base + ctz64u(y) : kNone;
+      const uint32_t in = y ? base + ctz64u(y) : kNone;
       cand = in < cand ? in : cand;
     }
-    const uint64_t topv = full ? pre + 64ull : (uint64_t)top1;
-    carry = rdlane((uint32_t)topv, 63u);  // at most ag < 2^32
+    const uint32_t topv = full ? pre + 64u : top1;
+    carry = rdlane(topv, 63u);
     return wave_min(cand);
   }
 
@@ -236,7 +238,7 @@ struct BitHeap {
     const uint32_t lane = lane_id();
     uint32_t n1 = (lo >> 12) + 1u;
     uint64_t r = load_node(n1 + lane);
-    uint64_t carry = 0;
+    uint32_t carry = 0;
     uint32_t K = word_step(lo >> 12, lo, s, carry);
     if (K != kNone) return K;
     while (n1 < nn && (uint64_t)kNodeGranules * n1 < below_end + s) {
@@ -246,13 +248,13 @@ struct BitHeap {
       const uint64_t lt = ballot(!full) & ((1ull << lane) - 1ull);
       const uint32_t ps = lt ? 63u - clz64u(lt) : 0u;
       const uint32_t tp = shfl(top1, ps);
-      const uint64_t pre = lt ? (uint64_t)tp + (uint64_t)kNodeGranules * (lane - 1u - ps)
-                              : carry + (uint64_t)kNodeGranules * lane;
+      const uint32_t pre = lt ? tp + kNodeGranules * (lane - 1u - ps)
+                              : carry + kNodeGranules * lane;
       // the first node where a run reaches its s-th granule
       const bool hit = (pre < s && pre + low1 >= s) || node_max(r) >= s;
       const uint32_t d = wave_min(hit && ni < nn ? ni : kNone);
       if (d != kNone) {
-        uint64_t c2 = rdlane((uint32_t)pre, d - n1);  // pre <= ag < 2^32
+        uint32_t c2 = rdlane(pre, d - n1);
         K = word_step(d, 0u, s, c2);
         if (K != kNone) return K;
         carry = c2;  // the summaries promised a run: not reached while they are exact
@@ -260,8 +262,8 @@ struct BitHeap {
         r = load_node(n1 + lane);
         continue;
       }
-      const uint64_t topv = full ? pre + kNodeGranules : (uint64_t)top1;
-      carry = rdlane((uint32_t)topv, 63u);
+      const uint32_t topv = full ? pre + kNodeGranules : top1;
+      carry = rdlane(topv, 63u);
       n1 += 64u;
       r = load_node(n1 + lane);
     }
