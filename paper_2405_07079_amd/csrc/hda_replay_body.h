@@ -160,7 +160,18 @@ __device__ __forceinline__ int64_t run_requests(const ReplayParams& p, Core& w, 
     const bool cut = !seg_like(ALGO) && ballot(is_free && w1 != 0u) != 0ull;
     uint32_t done;
     if (cut) {
-      done = run_block<ALGO, !seg_like(ALGO), false>(w, n, w0, w1, mfree, olo, ohi, st);
+      // (a partial free adds at most one free entry and keeps its live
+      // entry, so the block test holds for these blocks too)
+      if constexpr (UncheckedBlocks<Core>::value) {
+        if (w.block_safe(n)) {
+          done = run_block<ALGO, !seg_like(ALGO), true>(w, n, w0, w1, mfree, olo, ohi, st);
+          w.set_room();
+        } else {
+          done = run_block<ALGO, !seg_like(ALGO), false>(w, n, w0, w1, mfree, olo, ohi, st);
+        }
+      } else {
+        done = run_block<ALGO, !seg_like(ALGO), false>(w, n, w0, w1, mfree, olo, ohi, st);
+      }
     } else if constexpr (UncheckedBlocks<Core>::value) {
       if (w.block_safe(n)) {
         done = run_block<ALGO, false, true>(w, n, w0, w1, mfree, olo, ohi, st);
