@@ -7,8 +7,13 @@
 // implicit.
 //
 // The flags are summarised per node of 64 words (4,096 granules): the free
-// run at the node's bottom, the free run at its top and the longest free run
-// inside it, kept exact by every change of the flags.  A search reads the
+// run at the node's bottom and the free run at its top, kept exact by every
+// change of the flags, and a bound on the longest free run inside it.  A free
+// recomputes the whole summary; an allocation only takes granules away, so
+// it recomputes the two end runs and leaves the bound as it was (at least
+// the true longest run).  A search that trusts a stale bound finds no run in
+// that node's words, goes on past it with the exact end runs, and makes the
+// node's summary exact again from the words it read.  A search reads the
 // words of the rover's node (one word per lane), then the node summaries (one
 // node per lane), which name the first node where a long enough run reaches
 // its s-th granule, then that node's words: three dependent reads where a
@@ -79,7 +84,8 @@ __device__ __forceinline__ uint32_t longest_run(uint64_t w) {
 constexpr uint32_t kNodeGranules = 4096;  // 64 words
 
 // Node summary word: bottom run | top run << 16 | longest run << 32 (each
-// 0..4096 granules).  0 = no free granule.
+// 0..4096 granules; the longest run may be an upper bound).  0 = no free
+// granule.
 __device__ __forceinline__ uint32_t node_low(uint64_t r) { return (uint32_t)r & 0xffffu; }
 __device__ __forceinline__ uint32_t node_top(uint64_t r) { return (uint32_t)(r >> 16) & 0xffffu; }
 __device__ __forceinline__ uint32_t node_max(uint64_t r) { return (uint32_t)(r >> 32); }
@@ -114,6 +120,24 @@ __device__ __forceinline__ uint64_t node_summary(uint64_t w) {
   const uint32_t top = rdlane(topv, 63u);
   return (uint64_t)bottom | ((uint64_t)top << 16) | ((uint64_t)mx << 32);
 }
+
+// End runs of the node whose word `lane` is w (all lanes): bottom | top << 16,
+// the low half of its summary word.
+__device__ __forceinline__ uint32_t node_ends(uint64_t w) {
+  const bool full = w == ~0ull;
+  const uint32_t low1 = full ? 64u : ctz64u(~w);
+  const uint32_t top1 = full ? 64u : clz64u(~w);
+  const uint64_t nf = ballot(!full);
+  const uint32_t fl = nf ? ctz64u(nf) : 0u;         // lowest word not all free
+  const uint32_t hl = nf ? 63u - clz64u(nf) : 63u;  // highest
+  const uint32_t bottom = nf ? 64u * fl + rdlane(low1, fl) : kNodeGranules;
+  const uint32_t top = nf ? 64u * (63u - hl) + rdlane(top1, hl) : kNodeGranules;
+  return bottom | (top << 16);
+}
+
+// The low half of a summary word is written through this type, which may
+// alias the 64-bit word.
+typedef uint32_t __attribute__((may_alias)) sum_half_t;
 
 struct BitHeap {
   HDA_GLOBAL uint64_t* bits;   // nw words: bit i of word w = granule 64 w + i free
@@ -155,6 +179,12 @@ struct BitHeap {
     wave_sync();
     if (n < kn) lnodes[n] = v;  // every lane, same value
     else if (lane_id() == 0u) nodes[n] = v;
+  }
+  // the end runs alone (the low half of node n's summary word)
+  __device__ __forceinline__ void put_node_ends(uint32_t n, uint32_t v) const {
+    wave_sync();
+    if (n < kn) ((HDA_LDS sum_half_t*)lnodes)[2u * n] = v;  // every lane, same value
+    else if (lane_id() == 0u) ((HDA_GLOBAL sum_half_t*)nodes)[2u * n] = v;
   }
   // live entry i (wave-uniform), as the same value in every lane
   __device__ __forceinline__ Ent live_get(uint32_t i) const {
@@ -257,7 +287,10 @@ struct BitHeap {
         uint32_t c2 = rdlane(pre, d - n1);
         K = word_step(d, 0u, s, c2);
         if (K != kNone) return K;
-        carry = c2;  // the summaries promised a run: not reached while they are exact
+        // only a stale bound on d's longest run promises what d's words do
+        // not hold: the summary is made exact from them (left in cw)
+        put_node(d, node_summary(cw));
+        carry = c2;
         n1 = d + 1u;
         r = load_node(n1 + lane);
         continue;
@@ -272,7 +305,7 @@ struct BitHeap {
 
   // Granules [p, p + s) become free (set) or used (cleared), node by node:
   // each lane one word of the node (the words a search just read are reused),
-  // then the node's summary.
+  // then the node's summary (a free: all of it; an allocation: its end runs).
   __device__ void mark(uint32_t p, uint32_t s, bool set) {
     const uint32_t first = p >> 6, last = (p + s - 1u) >> 6;
     for (uint32_t n = p >> 12; n <= (last >> 6); ++n) {
@@ -295,8 +328,10 @@ struct BitHeap {
       if (in) bits[wi] = nv;
       cn = n;
       cw = nv;
-      const uint64_t sum = node_summary(nv);
-      put_node(n, sum);
+      if (set)
+        put_node(n, node_summary(nv));
+      else
+        put_node_ends(n, node_ends(nv));  // the longest run can only have shrunk
     }
   }
 

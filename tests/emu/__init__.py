@@ -63,6 +63,6 @@ def replay(batch, kf=64, kl=64, cf=4096, cl=4096, shape=2, overflowed=None):
                           P(so), P(sl), P(status), int(shape), kf, kl, cf, cl, P(syncs),
                           None if overflowed is None else P(overflowed))
     # 1: a bitmask heap's node summaries disagree with its flags
-    assert rc == 0, "bitmask node summaries are not exact" if rc == 1 else rc
+    assert rc == 0, "bitmask node summaries: end runs not exact or the longest-run bound below the true run" if rc == 1 else rc
     states = [state[so[h]:so[h] + sl[h]].copy() for h in range(H)]
     return res, states, status, syncs
