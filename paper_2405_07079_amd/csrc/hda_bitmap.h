@@ -152,7 +152,8 @@ struct BitHeap {
   uint32_t shift, ag, nw, nn;
   uint32_t L, rover, capL;
   uint32_t cn;  // node whose words the last word step or mark left in cw, or kNone
-  uint64_t cw;  // that node's word of this lane (no mask applied)
+  uint64_t cw;  // that node's word of this lane (no mask applied), always current:
+                // only mark changes flags, and it updates cw
 
   __device__ __forceinline__ BitHeap(uint64_t* b, uint64_t* nd, Ent* lv, HDA_LDS uint64_t* lnd,
                                      uint32_t n_lds_nodes, HDA_LDS Ent* llv, uint32_t n_lds_live,
@@ -231,8 +232,10 @@ struct BitHeap {
     const uint32_t wi = 64u * n + lane;
     const uint32_t lw = lo >> 6;
     const uint64_t below = wi < lw ? ~0ull : wi == lw ? (1ull << (lo & 63u)) - 1ull : 0ull;
-    cw = load(wi);
-    cn = n;
+    if (n != cn) {  // else cw holds the node's words as the last mark left them
+      cw = load(wi);
+      cn = n;
+    }
     const uint64_t w = cw & ~below;
     const bool full = w == ~0ull;
     const uint32_t low1 = full ? 64u : ctz64u(~w);   // free run at the bottom
@@ -304,7 +307,7 @@ struct BitHeap {
   }
 
   // Granules [p, p + s) become free (set) or used (cleared), node by node:
-  // each lane one word of the node (the words a search just read are reused),
+  // each lane one word of the node (words a search or mark left in cw are reused),
   // then the node's summary (a free: all of it; an allocation: its end runs).
   __device__ void mark(uint32_t p, uint32_t s, bool set) {
     const uint32_t first = p >> 6, last = (p + s - 1u) >> 6;
