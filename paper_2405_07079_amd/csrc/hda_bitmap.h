@@ -21,7 +21,8 @@
 // reaching the bottom of a lane's word (or node) from below is found from the
 // nearest lower lane that is not all free (a ballot, then a lane permute for
 // that lane's top run); a run that reaches s inside a word is found with s-1
-// shift-and steps.  The lowest start in the step is a wave-wide minimum.
+// shift-and steps.  The lowest start in the step is that of the lowest lane
+// holding one (a ballot).
 // Same rules as the other cores: values that feed a cross-lane operation are
 // computed by all lanes with selects, never under a lane-dependent branch.
 #pragma once
@@ -260,7 +261,12 @@ struct BitHeap {
     }
     const uint32_t topv = full ? pre + 64u : top1;
     carry = rdlane(topv, 63u);
-    return wave_min(cand);
+    // Candidates rise with the lane: each starts s free granules that end in
+    // its lane's word, and of two such runs the one ending in a lower word
+    // cannot start later.  So the lowest lane with a candidate holds the
+    // step's lowest start.
+    const uint64_t hc = ballot(cand != kNone);
+    return hc ? rdlane(cand, ctz64u(hc)) : kNone;
   }
 
   // The lowest p >= lo with granules [p, p + s) all free, or kNone.  Node
@@ -285,7 +291,8 @@ struct BitHeap {
                               : carry + kNodeGranules * lane;
       // the first node where a run reaches its s-th granule
       const bool hit = (pre < s && pre + low1 >= s) || node_max(r) >= s;
-      const uint32_t d = wave_min(hit && ni < nn ? ni : kNone);
+      const uint64_t hb = ballot(hit && ni < nn);
+      const uint32_t d = hb ? n1 + ctz64u(hb) : kNone;  // the lowest such node
       if (d != kNone) {
         uint32_t c2 = rdlane(pre, d - n1);
         K = word_step(d, 0u, s, c2);
