@@ -58,6 +58,17 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+# The workload the committed summaries under profiles/ were taken on: heaps,
+# requests per heap.  Their per-request figures are reported only for a run
+# of the same workload.
+PROFILED_WORKLOAD = (4096, 100_000)
+
+
+def profiled_workload(heaps, requests):
+    """True when a run replays the workload the committed summaries cover."""
+    return (heaps, requests) == PROFILED_WORKLOAD
+
+
 def recorded_traffic(algo_names):
     """HBM bytes per launch from the committed counter summary (FETCH_SIZE +
     WRITE_SIZE, calibrated on a copy kernel), averaged over the timed
@@ -524,6 +535,7 @@ def main():
               "heaps are independent, so N GPUs would each replay their own share "
               "with no communication -- run N=1.", file=sys.stderr)
         return 2
+    profiled = profiled_workload(args.heaps, args.requests)
 
     import torch
     from paper_2405_07079_amd import hda
@@ -662,7 +674,7 @@ def main():
                               "granules; next-fit search from the rover)",
                   "value": batch.requests / (float(np.median(bms)) / 1e3), "unit": "ops/s",
                   "launch_ms": float(np.median(bms))}
-        bitmap["issue"] = bitmap_issue(bitmap["value"])
+        bitmap["issue"] = (bitmap_issue(bitmap["value"]) if profiled else None)
         del bdb
         log(f"[bench] bitmap: {bitmap['value'] / 1e9:.3f} G ops/s")
 
@@ -763,7 +775,7 @@ def main():
     if c5:
         log(f"[bench] c5: {c5['value'] / 1e6:.2f} M ops/s ({c5['ms'] / 1e3:.1f} s)")
 
-    traffic = recorded_traffic([W.ALGO_NAMES[a] for a in algos])
+    traffic = recorded_traffic([W.ALGO_NAMES[a] for a in algos]) if profiled else None
     state_bytes = float(np.mean([int(dbs[a].state_len.sum().item()) * 8 for a in algos]))
     out = {
         "metric": METRIC,
@@ -806,9 +818,10 @@ def main():
                      # what the method's own structures would touch per request
                      # (oracle counters; 8 B per list entry, 24 B per record)
                      "metadata_bytes_per_request_oracle": meta_oracle,
-                     "lds_bank_conflict_cycles_per_request": recorded_lds_conflicts(),
-                     # what bounds this kernel: instruction issue (see DESIGN)
-                     "issue": issue_roofline(per_algo),
+                     "lds_bank_conflict_cycles_per_request": (
+                         recorded_lds_conflicts() if profiled else None),
+                     # what bounds this kernel: instruction issue
+                     "issue": issue_roofline(per_algo) if profiled else None,
                      "kernel": f"lean_kernel<{max(resolved['reg_free'], 0)}>",
                      "avg_launch_ms": avg_launch_s * 1e3,
                      "bytes_per_request": BYTES_PER_REQUEST,

@@ -44,6 +44,24 @@ def test_replay_issue_from_profile():
         assert m["valu_frac"] == pytest.approx(m["valu_per_request"] * ops / PEAK)
 
 
+def test_profile_figures_only_for_the_profiled_workload():
+    """The per-request counts and traffic of the committed summaries are
+    reported only for a run of the workload they were taken on, which each
+    summary's header names."""
+    heaps, requests = bench.PROFILED_WORKLOAD
+    assert bench.profiled_workload(heaps, requests)
+    assert not bench.profiled_workload(heaps, requests // 5)
+    assert not bench.profiled_workload(64, requests)
+    named = f"{heaps} heaps x {requests:,} requests"
+    for name in ("bitmap_4096x16MiB_instruction_mix.txt",
+                 "replay_4096x16MiB_instruction_mix.txt",
+                 "replay_4096x16MiB_hbm_traffic.txt",
+                 "replay_4096x16MiB_kernel_trace.txt"):
+        with open(os.path.join(ROOT, "profiles", name)) as f:
+            head = " ".join(f.read().split("\n")[:3])
+        assert named in head, name
+
+
 def test_more_than_one_gpu_is_refused():
     p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=300)
