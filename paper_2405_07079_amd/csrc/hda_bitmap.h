@@ -271,15 +271,15 @@ struct BitHeap {
 
   // The lowest p >= lo with granules [p, p + s) all free, or kNone.  Node
   // steps stop once they begin at or past below_end + s (only starts below
-  // below_end are wanted then).  The first node step's summaries are read
-  // together with the first word step's words.
+  // below_end are wanted then).  The summaries are read only once the word
+  // step over the rover's node has found nothing, as most searches end there.
   __device__ uint32_t find(uint32_t lo, uint32_t s, uint64_t below_end = 1ull << 40) {
     const uint32_t lane = lane_id();
     uint32_t n1 = (lo >> 12) + 1u;
-    uint64_t r = load_node(n1 + lane);
     uint32_t carry = 0;
     uint32_t K = word_step(lo >> 12, lo, s, carry);
     if (K != kNone) return K;
+    uint64_t r = load_node(n1 + lane);
     while (n1 < nn && (uint64_t)kNodeGranules * n1 < below_end + s) {
       const uint32_t ni = n1 + lane;
       const uint32_t low1 = node_low(r), top1 = node_top(r);
